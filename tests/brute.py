@@ -1,0 +1,67 @@
+"""Brute force written from the paper's dense-filter form (Sec. 3.2): for each
+hypothesis the filter F in R^{T x H x W} holds the PRF-weighted trajectory,
+and the score is the dot product of F with the inverse-variance-weighted data
+(eq. 4).  Independent of the oracle: its own offsets, profiles and loops, in
+plain Python floats.  Only usable on tiny inputs."""
+import math
+
+import numpy as np
+
+
+def anchor_phase(v, dt):
+    d = v * dt
+    a = math.floor(d + 0.5)
+    return a, d - a
+
+
+def profile(f, sigma_px, stamp, integrated=False):
+    h = stamp // 2
+    g = []
+    for b in range(-h, h + 1):
+        if integrated:
+            lo = (b - 0.5 - f) / sigma_px
+            hi = (b + 0.5 - f) / sigma_px
+            g.append(0.5 * (math.erf(hi / math.sqrt(2)) - math.erf(lo / math.sqrt(2))))
+        else:
+            g.append(math.exp(-0.5 * ((b - f) / sigma_px) ** 2))
+    s = sum(g)
+    return [x / s for x in g]
+
+
+def dense_filter(j, y0, x0, T, H, W, times, t_ref, vel, sigma_px, stamp, integrated=False):
+    F = np.zeros((T, H, W))
+    h = stamp // 2
+    for k in range(T):
+        ax, fx = anchor_phase(vel[j][0], times[k] - t_ref)
+        ay, fy = anchor_phase(vel[j][1], times[k] - t_ref)
+        gx = profile(fx, sigma_px, stamp, integrated)
+        gy = profile(fy, sigma_px, stamp, integrated)
+        for a in range(-h, h + 1):
+            for b in range(-h, h + 1):
+                Y, X = y0 + ay + a, x0 + ax + b
+                if 0 <= Y < H and 0 <= X < W:
+                    F[k, Y, X] = gy[a + h] * gx[b + h]
+    return F
+
+
+def ivar_map(sigma):
+    s = np.asarray(sigma, np.float64)
+    ok = np.isfinite(s) & (s > 0)
+    return np.where(ok, 1.0 / np.where(ok, s, 1.0) ** 2, 0.0)
+
+
+def search(R, sigma, times, t_ref, vel, sigma_px=0.7, stamp=5, integrated=False):
+    T, H, W = R.shape
+    J = len(vel)
+    iv = ivar_map(sigma)
+    D = np.asarray(R, np.float64) * iv[None]
+    nu = np.zeros((J, H, W))
+    lam = np.zeros((J, H, W))
+    for j in range(J):
+        for y0 in range(H):
+            for x0 in range(W):
+                F = dense_filter(j, y0, x0, T, H, W, times, t_ref, vel, sigma_px, stamp,
+                                 integrated)
+                nu[j, y0, x0] = float(np.sum(F * D))
+                lam[j, y0, x0] = float(np.sum(F * F * iv[None]))
+    return nu, lam
