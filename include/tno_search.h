@@ -1,0 +1,210 @@
+/*
+ * tno_search.h -- C ABI of the MI355X matched-filter trajectory search.
+ *
+ * Method (Ganapathi, arXiv:2209.09848, Sec. 3.2 "Matched Filter", eq. 4, and
+ * Sec. 3.3 "Interpreting Scores"): for every candidate constant-velocity
+ * trajectory j and every start pixel (x0, y0), the matched filter is the
+ * trajectory line convolved with the pixel response function (PRF); applying
+ * it is the dot product of filter and residual data, which estimates the
+ * object's total flux; the bank's maximum gives the most likely trajectory;
+ * scores above a threshold are candidates.  With the Gaussian noise model of
+ * Sec. 3.2 (per-pixel sigma, bright pixels clipped), the maximum-likelihood
+ * form is
+ *
+ *   ivar(y,x)  = 1/sigma(y,x)^2  (0 where sigma is <= 0 or not finite, and
+ *                                 0 off the image)
+ *   D          = v_j * (t_k - t_ref)   (per axis, FP64)
+ *   i = floor(D + 1/2), f = D - i      (anchor, sub-pixel phase)
+ *   W_jk(a,b)  = g(a; f_y) g(b; f_x), g the unit-sum Gaussian PRF profile
+ *   nu   = sum_k sum_ab W_jk(a,b) R_k(y0+i_y+a, x0+i_x+b) ivar(...)
+ *   Lam  = sum_k sum_ab W_jk(a,b)^2 ivar(...)
+ *   SNR  = nu / sqrt(Lam),  flux = nu / Lam   (0 where Lam == 0)
+ *
+ * Coordinates: x = column, y = row, pixel centres at integers.  All 2-D
+ * arrays are row-major [H][W]; the residual stack is [T][H][W].
+ *
+ * Calls on one handle are serialised internally; tno_search_destroy must not
+ * race other calls on the same handle.  No C++ exception crosses this ABI.
+ * On any error the out-parameters (handle, ticket) are not written and no
+ * output buffer is touched.
+ */
+#ifndef TNO_SEARCH_H
+#define TNO_SEARCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define TNO_OK 0
+#define TNO_PENDING 1          /* poll only: work not finished yet */
+#define TNO_E_INVAL (-1)       /* bad argument (message says which) */
+#define TNO_E_NOMEM (-2)       /* footprint can never fit the HBM budget, or allocation failed */
+#define TNO_E_BUSY (-3)        /* in-flight limit or budget full right now; retry later */
+#define TNO_E_DEVICE (-4)      /* HIP runtime or kernel error */
+#define TNO_E_TICKET (-5)      /* unknown ticket, or already collected */
+#define TNO_E_CANCELLED (-6)   /* request cancelled */
+#define TNO_E_INTERNAL (-7)    /* internal invariant broken */
+
+/* ---------------------------------------------------------------- enums */
+/* Storage type of the residual stack. */
+#define TNO_F32 0
+#define TNO_BF16 1             /* bfloat16 codes, per-tile power-of-two scales */
+#define TNO_F16 2              /* IEEE binary16 codes, per-tile scales */
+#define TNO_FP8_E4M3 3         /* OCP E4M3 "fn" codes, per-tile scales */
+
+/* PRF model (Sec. 2: PRF; Sec. 3.2: filter = trajectory line (x) PRF). */
+#define TNO_PRF_GAUSS_SAMPLED 0     /* exp(-(b-f)^2 / (2 s^2)) at pixel centres */
+#define TNO_PRF_GAUSS_INTEGRATED 1  /* Gaussian integrated over each pixel */
+
+/* Side of the square quantisation tiles of the reduced-precision stacks. */
+#define TNO_QTILE 64
+
+/* tno_config.flags */
+#define TNO_CFG_GRAPHS 1u           /* replay kernel sequences as HIP graphs */
+
+/* tno_request.flags */
+#define TNO_REQ_DEVICE_PTRS 1u      /* every input and output pointer is device memory */
+#define TNO_REQ_VALIDATE 2u         /* also scan inputs for non-finite values */
+
+/* Largest stamp side accepted (odd). */
+#define TNO_MAX_STAMP 15
+
+/* ---------------------------------------------------------------- types */
+typedef struct tno_search tno_search;   /* opaque handle */
+
+typedef struct {
+    int32_t device;              /* HIP device ordinal */
+    int32_t max_inflight;        /* tickets admitted at once (<= 0: 64) */
+    uint64_t hbm_budget_bytes;   /* device bytes the handle may hold (0: 90% of free) */
+    uint32_t flags;              /* TNO_CFG_* */
+    uint32_t reserved;           /* must be 0 */
+    void *stream;                /* hipStream_t to run on, or NULL for an own stream */
+    const char *tune_cache_path; /* JSON tuning cache, or NULL */
+} tno_config;
+
+typedef struct {
+    int32_t kind;                /* TNO_PRF_* */
+    int32_t stamp;               /* odd side S of the S x S stamp, 1..TNO_MAX_STAMP */
+    double sigma_px;             /* Gaussian sigma in pixels, > 0 */
+} tno_prf;
+
+typedef struct {
+    int32_t height, width;       /* H, W > 0 */
+    int32_t n_frames;            /* T > 0 */
+    int32_t dtype;               /* TNO_F32 / TNO_BF16 / TNO_F16 / TNO_FP8_E4M3 */
+    const void *residuals;       /* [T][H][W] of dtype (float, or uint16/uint8 codes) */
+    const float *tile_scales;    /* [T][ceil(H/64)][ceil(W/64)]: value = code * scale;
+                                    required unless dtype == TNO_F32 */
+    const float *sigma;          /* [H][W] per-pixel noise sigma */
+    const double *times;         /* [T] frame times, any finite values (gaps allowed) */
+    double t_ref;                /* reference time of the start pixel; NaN: times[0] */
+    tno_prf prf;
+    int32_t n_traj;              /* J >= 1 */
+    int32_t top_k;               /* candidates wanted, 0..TNO_MAX_TOPK */
+    const double *velocities;    /* [J][2] = (vx, vy) in pixels per unit of `times` */
+    uint64_t stack_key;          /* 0, or a key under which the prepared stack stays
+                                    resident for later requests on the same data */
+    uint32_t flags;              /* TNO_REQ_* */
+    uint32_t reserved;           /* must be 0 */
+} tno_request;
+
+#define TNO_MAX_TOPK 1024
+
+typedef struct {
+    float snr, flux;
+    int32_t y, x;                /* start pixel of the trajectory's best score */
+} tno_peak;
+
+typedef struct {
+    float snr, flux;
+    int32_t traj, y, x;
+} tno_candidate;
+
+/* Outputs; every pointer may be NULL (= not produced).  Host or device memory
+ * according to TNO_REQ_DEVICE_PTRS.  Caller-owned; written only between a
+ * successful submit and the ticket's terminal poll. */
+typedef struct {
+    float *snr;                  /* [J][H][W] */
+    float *flux;                 /* [J][H][W] */
+    float *best_snr;             /* [H][W] max over the bank, ties to the lowest j */
+    int32_t *best_traj;          /* [H][W] arg-max j */
+    tno_peak *traj_max;          /* [J] per-trajectory max, ties to the smallest y*W+x */
+    tno_candidate *topk;         /* [top_k] SNR descending, then j*H*W+y*W+x ascending */
+} tno_outputs;
+
+typedef struct {
+    int32_t status;              /* TNO_OK or a TNO_E_* code */
+    int32_t n_topk;              /* candidates written (min(top_k, J*H*W)) */
+    uint64_t updates;            /* J*H*W*T (trajectory x pixel x frame terms) */
+    double queue_ms;             /* total_ms - device_ms (host staging, queueing, polling) */
+    double device_ms;            /* device start -> device end (HIP events) */
+    double total_ms;             /* submit -> completion seen by poll */
+    /* device time per phase (HIP events on the request's stream): */
+    double prep_ms;              /* ivar and the inverse-variance-weighted stack */
+    double table_ms;             /* FP64 offset/PRF table and trail kernels */
+    double lambda_ms;            /* FP64 normaliser */
+    double search_ms;            /* numerator gather-stencil + SNR/flux epilogue */
+    double reduce_ms;            /* bank maximum, per-trajectory maximum, top-k, copies */
+    char message[160];           /* human-readable detail for errors */
+} tno_result;
+
+/* ---------------------------------------------------------------- calls */
+
+/* Create a search handle on cfg->device.  Returns TNO_OK and writes
+ * *out_handle, or TNO_E_INVAL (NULL args, reserved != 0), TNO_E_DEVICE (no
+ * such device / HIP failure).  The handle owns its device memory. */
+int tno_search_create(const tno_config *cfg, tno_search **out_handle);
+
+/* Enqueue one search (Sec. 3.2 eq. 4 over the whole trajectory bank, then the
+ * Sec. 3.2/3.3 reductions).  Host inputs are fully read before the call
+ * returns; with TNO_REQ_DEVICE_PTRS inputs are borrowed until the terminal
+ * poll and must stay unmodified.  Returns TNO_OK and writes *out_ticket, or
+ * TNO_E_INVAL / TNO_E_NOMEM / TNO_E_BUSY / TNO_E_DEVICE; on error nothing is
+ * enqueued.  tno_search_last_error() holds the message of a refusal. */
+int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *out,
+                      uint64_t *out_ticket);
+
+/* Wait up to timeout_ms (0: just test, < 0: forever) for a ticket.  Returns
+ * TNO_PENDING if not finished (out_result untouched), else the terminal status,
+ * filling *out_result; the ticket is then retired (a second poll gives
+ * TNO_E_TICKET). */
+int tno_search_poll(tno_search *h, uint64_t ticket, int32_t timeout_ms, tno_result *out_result);
+
+/* Cancel pending work, free every device buffer, destroy the handle.
+ * destroy(NULL) is a no-op. */
+void tno_search_destroy(tno_search *h);
+
+/* Quantise an FP32 residual stack into reduced-precision codes with one
+ * power-of-two scale per frame and 64x64 tile (the precision form's storage;
+ * the paper states no precision).  For tile amax > 0 the scale is
+ * s = 2^(ceil(log2 amax) - E), E = 8 for TNO_FP8_E4M3 and 15 for TNO_BF16 /
+ * TNO_F16, else s = 1; codes hold round-to-nearest-even R/s (E4M3 saturates at
+ * 448), so code * s is exact in FP32.  All pointers are device memory:
+ * residuals [T][H][W] float, codes [T][H][W] (uint16 or uint8), tile_scales
+ * [T][ceil(H/64)][ceil(W/64)] float.  Enqueued on `stream` (a hipStream_t, or
+ * NULL for the null stream); returns TNO_OK, TNO_E_INVAL or TNO_E_DEVICE. */
+int tno_quantize(int32_t n_frames, int32_t height, int32_t width, int32_t dtype,
+                 const float *residuals, void *codes, float *tile_scales, void *stream);
+
+/* ---------------------------------------------------------------- host-only helpers */
+
+/* Check a request and outputs without touching a GPU (the same checks submit
+ * makes).  Returns TNO_OK or TNO_E_INVAL; writes a message of up to len bytes
+ * to msg if msg is not NULL. */
+int tno_search_validate(const tno_request *req, const tno_outputs *out, char *msg, int32_t len);
+
+/* Device bytes a request needs while in flight (inputs staged on the device,
+ * internal buffers, outputs produced internally).  0 if the request is invalid. */
+uint64_t tno_search_footprint(const tno_request *req, const tno_outputs *out);
+
+/* Message of the last refused call on this thread (empty if none). */
+const char *tno_search_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TNO_SEARCH_H */

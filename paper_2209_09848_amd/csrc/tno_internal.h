@@ -1,0 +1,91 @@
+// tno_internal.h -- shared declarations of the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tno {
+
+// Search tile: 128 start-pixel columns (2 per lane) x 32 rows (8 per lane, 4 waves).
+constexpr int SEARCH_TX = 128;
+constexpr int SEARCH_TY = 32;
+constexpr int SEARCH_THREADS = 256;
+// Normaliser tile: 64 columns (1 per lane) x 32 rows (8 per lane, 4 waves).
+constexpr int LAMBDA_TX = 64;
+constexpr int LAMBDA_TY = 32;
+// Frames summed in FP32 before each FP64 accumulation of the numerator.
+constexpr int FRAME_CHUNK = 8;
+
+// Dwords per offset/weight table entry: iy, ix, gy[S], gx[S], padded to 16 bytes.
+__host__ __device__ constexpr int table_stride(int S) { return (2 + 2 * S + 3) & ~3; }
+
+// Per-trajectory layout of the collapsed trail kernel K_j (column runs).
+struct TrailInfo {
+    int32_t qx0;       // first column offset of the trail box
+    int32_t ncols;     // columns in the box (clipped to |qx| < W)
+    int32_t qy_lo;     // smallest row offset kept (clipped to > -H)
+    int32_t qy_hi;     // largest row offset kept (clipped to < H)
+    int32_t cap;       // capacity of one column run
+    int32_t pad;
+    int64_t col_off;   // index of this trajectory's first column record
+    int64_t val_off;   // index of this trajectory's first K value
+};
+
+// Radix-select state of the exact top-k.
+struct TopkState {
+    uint32_t prefix;   // key bits fixed so far
+    uint32_t mask;     // which bits are fixed
+    int32_t k_rem;     // rank still to find among keys matching prefix
+    uint32_t n_gt;     // candidates strictly above the threshold written
+    uint32_t hist[256];
+};
+
+struct SearchArgs {
+    const float4 *Z4;        // padded inverse-variance-weighted stack [T][Hp][Wp4] float4
+    const int32_t *tab32;    // [J][T][table_stride(S)]
+    const double *lam;       // [J][H][W]
+    float *snr;              // [J][H][W]
+    float *flux;             // [J][H][W]
+    uint64_t *tile_keys;     // [J][ntiles]
+    int H, W, T, J;
+    int Hp, Wp4, Pt, Pl;
+    int ntx, nty, n_items;
+};
+
+struct LambdaArgs {
+    const TrailInfo *info;
+    const int2 *colmeta;     // per column: (row offset of run start, run length)
+    const double *kvals;
+    const double *ivar64;    // [H][W]
+    double *lam;             // [J][H][W]
+    int H, W, J, ntx, nty, n_items;
+};
+
+// ---- launch wrappers (all on `st`; return hipError_t of the launch)
+hipError_t launch_zero(hipStream_t st, int32_t *p, int n);
+hipError_t launch_ivar(hipStream_t st, int HW, const float *sigma, float *ivar32, double *ivar64);
+hipError_t launch_prep_z(hipStream_t st, int dtype, const void *R, const float *scales,
+                         const float *ivar32, float4 *Z4, int T, int H, int W, int Hp, int Wp4,
+                         int Pt, int Pl);
+hipError_t launch_table(hipStream_t st, int J, int T, const double *times, double t_ref,
+                        const double *vel, int kind, double sigma_px, int S, int32_t *tab32,
+                        double *tab64);
+hipError_t launch_trail(hipStream_t st, int J, int T, int S, int H, const int32_t *tab32,
+                        const double *tab64, const TrailInfo *info, int2 *colmeta,
+                        double *kvals, int32_t *err);
+hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a);
+hipError_t launch_search(hipStream_t st, int S, const SearchArgs &a);
+hipError_t launch_trajmax(hipStream_t st, int J, int ntiles, int W, int HW,
+                          const uint64_t *tile_keys, const float *snr, const float *flux,
+                          void *traj_max_out);
+hipError_t launch_best(hipStream_t st, int J, int HW, const float *snr, float *best_snr,
+                       int32_t *best_traj);
+hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int64_t N, int HW,
+                       int W, int k, TopkState *state, uint32_t *chunk_cnt, int64_t n_chunks,
+                       uint64_t *cand, void *topk_out);
+hipError_t launch_quantize(hipStream_t st, int dtype, const float *R, int T, int H, int W,
+                           void *codes, float *scales);
+
+constexpr int TOPK_CHUNK = 8192;
+
+}  // namespace tno

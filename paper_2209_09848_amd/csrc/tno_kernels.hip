@@ -1,0 +1,948 @@
+// tno_kernels.hip -- gfx950 kernels of the matched-filter trajectory search
+// (arXiv:2209.09848, Sec. 3.2 eq. 4 and Sec. 3.3).
+//
+// Pipeline of one request (all on one HIP stream):
+//   k_ivar      ivar = 1/sigma^2 (FP64, also rounded to FP32); 0 for masked pixels
+//   k_prep_z    Z = decode(R) * ivar into a zero-padded FP32 stack (float4 rows)
+//   k_table     per (trajectory, frame): FP64 anchor/phase and PRF profiles
+//   k_trail     per trajectory: collapsed trail kernel K_j(q) = sum_k W_jk^2 at q (FP64)
+//   k_lambda    Lam_j = ivar (x) K_j, a sparse FP64 correlation
+//   k_search    nu_j = sum_k W_jk (x) Z_k at the frame's shift; LDS-staged window,
+//               separable PRF, FP32 frame chunks into FP64 totals; epilogue
+//               SNR = nu/sqrt(Lam), flux = nu/Lam, per-tile maximum key
+//   k_trajmax / k_best / top-k   the reductions of Sec. 3.2-3.3
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+#include <limits.h>
+
+#include "tno_internal.h"
+#include "../../include/tno_search.h"
+
+namespace tno {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ uint32_t ordered_key(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float key_to_float(uint32_t k)
+{
+    uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+    return __uint_as_float(u);
+}
+
+// Work-item index of block b when items are dealt to the 8 XCDs in contiguous
+// ranges: consecutive blocks go round-robin to XCDs, so block b runs on XCD
+// b % 8; giving each XCD a contiguous item range keeps the trajectories of one
+// tile (which read the same frame region) on one XCD and its L2.
+__device__ __forceinline__ int xcd_item(int b, int nblocks)
+{
+    int per = nblocks >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+__host__ static int xcd_grid(int n_items)
+{
+    int per = (n_items + 7) / 8;
+    return per * 8;
+}
+
+// ------------------------------------------------------------------ k_zero
+
+// Clears small device counters with a kernel (no memset nodes in the stream).
+__global__ void k_zero(int32_t *p, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+hipError_t launch_zero(hipStream_t st, int32_t *p, int n)
+{
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, p, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k_ivar
+
+__global__ void k_ivar(int HW, const float *__restrict__ sigma, float *__restrict__ ivar32,
+                       double *__restrict__ ivar64)
+{
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += gridDim.x * blockDim.x) {
+        double s = (double)sigma[p];
+        double iv = (__builtin_isfinite(s) && s > 0.0) ? 1.0 / (s * s) : 0.0;
+        ivar64[p] = iv;
+        ivar32[p] = (float)iv;
+    }
+}
+
+hipError_t launch_ivar(hipStream_t st, int HW, const float *sigma, float *ivar32, double *ivar64)
+{
+    int blocks = (HW + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_ivar, dim3(blocks), dim3(256), 0, st, HW, sigma, ivar32, ivar64);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ decode + k_prep_z
+
+__device__ __forceinline__ float decode_e4m3(uint32_t c)
+{
+    // E4M3fn code -> binary16 with the same sign/exponent/mantissa bits shifted
+    // into place: value(binary16) = value(E4M3) * 2^-8 for normals and
+    // subnormals alike; the caller's scale absorbs the 2^8.
+    uint16_t hb = (uint16_t)(((c & 0x80u) << 8) | ((c & 0x7Fu) << 7));
+    _Float16 hv;
+    __builtin_memcpy(&hv, &hb, 2);
+    return (float)hv;
+}
+
+template <int DT>
+__device__ __forceinline__ float load_residual(const void *R, const float *scales, size_t idx,
+                                               int k, int y, int x, int nqy, int nqx)
+{
+    if constexpr (DT == TNO_F32) {
+        return ((const float *)R)[idx];
+    } else {
+        float s = scales[((size_t)k * nqy + (y >> 6)) * nqx + (x >> 6)];
+        if constexpr (DT == TNO_BF16) {
+            uint32_t b = ((const uint16_t *)R)[idx];
+            return __uint_as_float(b << 16) * s;
+        } else if constexpr (DT == TNO_F16) {
+            _Float16 hv = ((const _Float16 *)R)[idx];
+            return (float)hv * s;
+        } else {
+            uint32_t c = ((const uint8_t *)R)[idx];
+            return decode_e4m3(c) * (s * 256.0f);
+        }
+    }
+}
+
+// One thread per float4 group of the padded stack; grid (groups/256, Hp, T).
+template <int DT>
+__global__ void k_prep_z(const void *__restrict__ R, const float *__restrict__ scales,
+                         const float *__restrict__ ivar32, float4 *__restrict__ Z4, int H, int W,
+                         int Hp, int Wp4, int Pt, int Pl)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= Wp4)
+        return;
+    int yp = blockIdx.y;
+    int k = blockIdx.z;
+    int y = yp - Pt;
+    int nqy = (H + TNO_QTILE - 1) / TNO_QTILE, nqx = (W + TNO_QTILE - 1) / TNO_QTILE;
+    float v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        int x = 4 * g + e - Pl;
+        v[e] = 0.0f;
+        if (y >= 0 && y < H && x >= 0 && x < W) {
+            size_t p = (size_t)y * W + x;
+            float r = load_residual<DT>(R, scales, (size_t)k * H * W + p, k, y, x, nqy, nqx);
+            v[e] = r * ivar32[p];
+        }
+    }
+    Z4[((size_t)k * Hp + yp) * Wp4 + g] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+hipError_t launch_prep_z(hipStream_t st, int dtype, const void *R, const float *scales,
+                         const float *ivar32, float4 *Z4, int T, int H, int W, int Hp, int Wp4,
+                         int Pt, int Pl)
+{
+    dim3 grid((Wp4 + 255) / 256, Hp, T);
+    switch (dtype) {
+    case TNO_F32:
+        hipLaunchKernelGGL(k_prep_z<TNO_F32>, grid, dim3(256), 0, st, R, scales, ivar32, Z4, H, W, Hp, Wp4, Pt, Pl);
+        break;
+    case TNO_BF16:
+        hipLaunchKernelGGL(k_prep_z<TNO_BF16>, grid, dim3(256), 0, st, R, scales, ivar32, Z4, H, W, Hp, Wp4, Pt, Pl);
+        break;
+    case TNO_F16:
+        hipLaunchKernelGGL(k_prep_z<TNO_F16>, grid, dim3(256), 0, st, R, scales, ivar32, Z4, H, W, Hp, Wp4, Pt, Pl);
+        break;
+    default:
+        hipLaunchKernelGGL(k_prep_z<TNO_FP8_E4M3>, grid, dim3(256), 0, st, R, scales, ivar32, Z4, H, W, Hp, Wp4, Pt, Pl);
+        break;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k_table (FP64)
+
+// Phi(hi) - Phi(lo) of the standard normal, using erfc in the tails.
+__device__ double normal_mass(double lo, double hi)
+{
+    const double r2 = 0.70710678118654752440;
+    if (lo >= 0.0)
+        return 0.5 * (erfc(lo * r2) - erfc(hi * r2));
+    if (hi <= 0.0)
+        return 0.5 * (erfc(-hi * r2) - erfc(-lo * r2));
+    return 0.5 * (erf(hi * r2) - erf(lo * r2));
+}
+
+// Unit-sum profile of the Gaussian PRF at phase f over taps -h..h.
+__device__ void prf_profile(int kind, double sp, int S, double f, double *g)
+{
+#pragma clang fp contract(off)
+    int h = S / 2;
+    double sum = 0.0;
+    for (int b = -h; b <= h; ++b) {
+        double v;
+        if (kind == TNO_PRF_GAUSS_INTEGRATED) {
+            v = normal_mass(((double)b - 0.5 - f) / sp, ((double)b + 0.5 - f) / sp);
+        } else {
+            double u = (double)b - f;
+            v = exp(-(u * u) / (2.0 * sp * sp));
+        }
+        g[b + h] = v;
+        sum += v;
+    }
+    for (int b = 0; b < S; ++b)
+        g[b] = g[b] / sum;
+}
+
+// One thread per (trajectory j, frame k): anchor i = floor(v*dt + 1/2) and
+// phase f = v*dt - i per axis in FP64 without fused multiply-add (the anchor
+// must flip exactly where the definition flips), then both profiles.
+__global__ void k_table(int J, int T, const double *__restrict__ times, double t_ref,
+                        const double *__restrict__ vel, int kind, double sp, int S,
+                        int32_t *__restrict__ tab32, double *__restrict__ tab64)
+{
+#pragma clang fp contract(off)
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= J * T)
+        return;
+    int j = e / T, k = e - j * T;
+    double dt = times[k] - t_ref;
+    double dx = vel[2 * j + 0] * dt;
+    double dy = vel[2 * j + 1] * dt;
+    double ax = floor(dx + 0.5), ay = floor(dy + 0.5);
+    double fx = dx - ax, fy = dy - ay;
+    double gy[TNO_MAX_STAMP], gx[TNO_MAX_STAMP];
+    prf_profile(kind, sp, S, fy, gy);
+    prf_profile(kind, sp, S, fx, gx);
+    const int TS = table_stride(S);
+    int32_t *t = tab32 + (size_t)e * TS;
+    t[0] = (int32_t)ay;
+    t[1] = (int32_t)ax;
+    for (int s = 0; s < S; ++s) {
+        t[2 + s] = __float_as_int((float)gy[s]);
+        t[2 + S + s] = __float_as_int((float)gx[s]);
+    }
+    for (int s = 2 + 2 * S; s < TS; ++s)
+        t[s] = 0;
+    double *t64 = tab64 + (size_t)e * 2 * S;
+    for (int s = 0; s < S; ++s) {
+        t64[s] = gy[s];
+        t64[S + s] = gx[s];
+    }
+}
+
+hipError_t launch_table(hipStream_t st, int J, int T, const double *times, double t_ref,
+                        const double *vel, int kind, double sigma_px, int S, int32_t *tab32,
+                        double *tab64)
+{
+    int n = J * T;
+    hipLaunchKernelGGL(k_table, dim3((n + 127) / 128), dim3(128), 0, st, J, T, times, t_ref, vel,
+                       kind, sigma_px, S, tab32, tab64);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k_trail (FP64)
+
+// One block per trajectory, one thread per column offset qx of the trail box.
+// K_j(qy, qx) = sum_k gx_k(qx - ix_k)^2 gy_k(qy - iy_k)^2 over the frames whose
+// stamp covers (qy, qx); each column is one contiguous run of rows, summed
+// frame by frame in frame order (deterministic).
+__global__ void k_trail(int T, int S, const int32_t *__restrict__ tab32,
+                        const double *__restrict__ tab64, const TrailInfo *__restrict__ info,
+                        int2 *__restrict__ colmeta, double *__restrict__ kvals,
+                        int32_t *__restrict__ err)
+{
+    const int j = blockIdx.x;
+    const TrailInfo ti = info[j];
+    const int h = S / 2;
+    const int TS = table_stride(S);
+    const int32_t *tj = tab32 + (size_t)j * T * TS;
+    const double *t64 = tab64 + (size_t)j * T * 2 * S;
+    for (int c = threadIdx.x; c < ti.ncols; c += blockDim.x) {
+        const int qx = ti.qx0 + c;
+        int lo = INT_MAX, hi = INT_MIN;
+        for (int k = 0; k < T; ++k) {
+            int ix = tj[(size_t)k * TS + 1];
+            int dxo = qx - ix;
+            if (dxo >= -h && dxo <= h) {
+                int iy = tj[(size_t)k * TS + 0];
+                lo = min(lo, iy - h);
+                hi = max(hi, iy + h);
+            }
+        }
+        lo = max(lo, ti.qy_lo);
+        hi = min(hi, ti.qy_hi);
+        int len = hi >= lo ? hi - lo + 1 : 0;
+        if (len > ti.cap) {
+            atomicOr(err, 1);
+            len = 0;
+        }
+        colmeta[ti.col_off + c] = make_int2(lo, len);
+        double *kv = kvals + ti.val_off + (int64_t)c * ti.cap;
+        for (int i = 0; i < len; ++i)
+            kv[i] = 0.0;
+        if (len == 0)
+            continue;
+        for (int k = 0; k < T; ++k) {
+            int ix = tj[(size_t)k * TS + 1];
+            int dxo = qx - ix;
+            if (dxo < -h || dxo > h)
+                continue;
+            int iy = tj[(size_t)k * TS + 0];
+            double wx = t64[(size_t)k * 2 * S + S + dxo + h];
+            double wx2 = wx * wx;
+            for (int a = 0; a < S; ++a) {
+                int r = iy - h + a - lo;
+                if (r < 0 || r >= len)
+                    continue;
+                double wy = t64[(size_t)k * 2 * S + a];
+                kv[r] += wx2 * (wy * wy);
+            }
+        }
+    }
+}
+
+hipError_t launch_trail(hipStream_t st, int J, int T, int S, int H, const int32_t *tab32,
+                        const double *tab64, const TrailInfo *info, int2 *colmeta,
+                        double *kvals, int32_t *err)
+{
+    (void)H;
+    hipLaunchKernelGGL(k_trail, dim3(J), dim3(256), 0, st, T, S, tab32, tab64, info, colmeta,
+                       kvals, err);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k_lambda (FP64)
+
+// Lam_j(y, x) = sum over trail columns qx, rows qy of K_j(qy, qx) ivar(y+qy, x+qx).
+// A lane owns one column x and 8 consecutive rows; per trail column it walks a
+// register window down the image column so that each ivar load serves up to 8
+// outputs.  The K values are uniform across the wave (scalar loads).
+__global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
+{
+    constexpr int R = 8;
+    int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= a.n_items)
+        return;
+    const int j = item % a.J;
+    const int tile = item / a.J;
+    const int tyi = tile / a.ntx, txi = tile - tyi * a.ntx;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int x = txi * LAMBDA_TX + lane;
+    const int y0 = tyi * LAMBDA_TY + wv * R;
+    const TrailInfo ti = a.info[j];
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        acc[r] = 0.0;
+    for (int c = 0; c < ti.ncols; ++c) {
+        const int2 m = a.colmeta[ti.col_off + c];
+        const int len = m.y;
+        if (len == 0)
+            continue;
+        const int X = x + ti.qx0 + c;
+        const bool xin = (unsigned)X < (unsigned)a.W;
+        const double *kv = a.kvals + ti.val_off + (int64_t)c * ti.cap;
+        for (int i = 0; i < len + R - 1; ++i) {
+            const int Y = y0 + m.x + i;
+            double v = 0.0;
+            if (xin && (unsigned)Y < (unsigned)a.H)
+                v = a.ivar64[(size_t)Y * a.W + X];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int q = i - r;
+                if (q >= 0 && q < len)
+                    acc[r] = fma(kv[q], v, acc[r]);
+            }
+        }
+    }
+    if (x < a.W) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int y = y0 + r;
+            if (y < a.H)
+                a.lam[((size_t)j * a.H + y) * a.W + x] = acc[r];
+        }
+    }
+}
+
+hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a)
+{
+    hipLaunchKernelGGL(k_lambda, dim3(xcd_grid(a.n_items)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k_search
+
+// One block = one (tile of 128x32 start pixels, trajectory).  Per frame k the
+// block stages the window the tile's stamps cover at the frame's integer
+// shift -- (32+S-1) rows x (128+S-1) columns of Z -- into LDS with aligned
+// float4 loads (the sub-float4 offset d is applied when reading), then every
+// lane evaluates the separable stamp for its 2 columns x 8 rows: a horizontal
+// pass of S taps per window row, streamed into a vertical pass of S taps.
+// The PRF taps and shift are wave-uniform (scalar loads of the table entry).
+// Frame partials accumulate in FP32 over FRAME_CHUNK frames, then into FP64.
+template <int S>
+__global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a)
+{
+    constexpr int h = S / 2;
+    constexpr int CPL = 2, RPL = 8;
+    constexpr int TX = SEARCH_TX, TY = SEARCH_TY;
+    constexpr int WY = TY + S - 1;
+    constexpr int NG = (TX + S - 1 + 3 + 3) / 4;
+    constexpr int LS = NG * 4;
+    constexpr int TS = table_stride(S);
+    constexpr int NV = CPL + S - 1;
+    __shared__ float4 win4[WY * NG];
+
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= a.n_items)
+        return;
+    const int j = item % a.J;
+    const int tile = item / a.J;
+    const int tyi = tile / a.ntx, txi = tile - tyi * a.ntx;
+    const int ty0 = tyi * TY, tx0 = txi * TX;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const float *win = reinterpret_cast<const float *>(win4);
+
+    float part[RPL][CPL];
+    double acc[RPL][CPL];
+#pragma unroll
+    for (int o = 0; o < RPL; ++o)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            part[o][c] = 0.0f;
+            acc[o][c] = 0.0;
+        }
+
+    const int32_t *tabj = a.tab32 + (size_t)j * a.T * TS;
+    const size_t frame4 = (size_t)a.Hp * a.Wp4;
+    for (int k = 0; k < a.T; ++k) {
+        const int32_t *e = tabj + (size_t)k * TS;
+        const int iy = e[0], ix = e[1];
+        float gy[S], gx[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            gy[s] = __int_as_float(e[2 + s]);
+            gx[s] = __int_as_float(e[2 + S + s]);
+        }
+        const int oy = ty0 + iy - h + a.Pt;
+        const int ox = tx0 + ix - h + a.Pl;
+        const int ag = ox >> 2;          // floor division (arithmetic shift)
+        const int d = ox - (ag << 2);    // 0..3
+        const float4 *Zk = a.Z4 + (size_t)k * frame4;
+        for (int idx = threadIdx.x; idx < WY * NG; idx += SEARCH_THREADS) {
+            const int r = idx / NG;
+            const int g = idx - r * NG;
+            const int yp = oy + r, gp = ag + g;
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if ((unsigned)yp < (unsigned)a.Hp && (unsigned)gp < (unsigned)a.Wp4)
+                v = Zk[(size_t)yp * a.Wp4 + gp];
+            win4[idx] = v;
+        }
+        __syncthreads();
+
+        const float *base = win + (wv * RPL) * LS + CPL * lane + d;
+#pragma unroll
+        for (int rr = 0; rr < RPL + S - 1; ++rr) {
+            float v[NV];
+#pragma unroll
+            for (int t = 0; t < NV; ++t)
+                v[t] = base[rr * LS + t];
+            float hs[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                float s = gx[0] * v[c];
+#pragma unroll
+                for (int b = 1; b < S; ++b)
+                    s = fmaf(gx[b], v[c + b], s);
+                hs[c] = s;
+            }
+#pragma unroll
+            for (int aa = 0; aa < S; ++aa) {
+                const int o = rr - aa;
+                if (o >= 0 && o < RPL) {
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c)
+                        part[o][c] = fmaf(gy[aa], hs[c], part[o][c]);
+                }
+            }
+        }
+        __syncthreads();
+        if ((k % FRAME_CHUNK) == FRAME_CHUNK - 1) {
+#pragma unroll
+            for (int o = 0; o < RPL; ++o)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    acc[o][c] += (double)part[o][c];
+                    part[o][c] = 0.0f;
+                }
+        }
+    }
+
+    // epilogue: SNR and flux, and the tile's largest (SNR, -pixel) key
+    uint64_t best = 0;
+    const size_t HW = (size_t)a.H * a.W;
+#pragma unroll
+    for (int o = 0; o < RPL; ++o) {
+        const int y = ty0 + wv * RPL + o;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int x = tx0 + CPL * lane + c;
+            if (y < a.H && x < a.W) {
+                const double nu = acc[o][c] + (double)part[o][c];
+                const size_t p = (size_t)y * a.W + x;
+                const size_t mp = (size_t)j * HW + p;
+                const double L = a.lam[mp];
+                float snr = 0.0f, flux = 0.0f;
+                if (L > 0.0) {
+                    snr = (float)(nu / sqrt(L));
+                    flux = (float)(nu / L);
+                }
+                snr = snr + 0.0f;    // -0 -> +0 so equal scores compare equal as keys
+                flux = flux + 0.0f;
+                if (a.snr)
+                    a.snr[mp] = snr;
+                if (a.flux)
+                    a.flux[mp] = flux;
+                uint64_t key = ((uint64_t)ordered_key(snr) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)p);
+                best = key > best ? key : best;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        uint64_t o = __shfl_xor(best, off, 64);
+        best = o > best ? o : best;
+    }
+    __shared__ uint64_t wbest[SEARCH_THREADS / 64];
+    if (lane == 0)
+        wbest[wv] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t m = wbest[0];
+        for (int w = 1; w < SEARCH_THREADS / 64; ++w)
+            m = wbest[w] > m ? wbest[w] : m;
+        a.tile_keys[(size_t)j * (a.ntx * a.nty) + tile] = m;
+    }
+}
+
+hipError_t launch_search(hipStream_t st, int S, const SearchArgs &a)
+{
+    dim3 grid(xcd_grid(a.n_items)), block(SEARCH_THREADS);
+    switch (S) {
+    case 1: hipLaunchKernelGGL(k_search<1>, grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_search<3>, grid, block, 0, st, a); break;
+    case 5: hipLaunchKernelGGL(k_search<5>, grid, block, 0, st, a); break;
+    case 7: hipLaunchKernelGGL(k_search<7>, grid, block, 0, st, a); break;
+    case 9: hipLaunchKernelGGL(k_search<9>, grid, block, 0, st, a); break;
+    case 11: hipLaunchKernelGGL(k_search<11>, grid, block, 0, st, a); break;
+    case 13: hipLaunchKernelGGL(k_search<13>, grid, block, 0, st, a); break;
+    case 15: hipLaunchKernelGGL(k_search<15>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ reductions
+
+// Per trajectory: the largest tile key; ties in SNR go to the smallest pixel
+// index because the key stores 0xFFFFFFFF - (y*W + x) in its low half.
+__global__ void k_trajmax(int ntiles, int W, int HW, const uint64_t *__restrict__ tile_keys,
+                          const float *__restrict__ snr, const float *__restrict__ flux,
+                          tno_peak *__restrict__ out)
+{
+    const int j = blockIdx.x;
+    uint64_t m = 0;
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        uint64_t v = tile_keys[(size_t)j * ntiles + t];
+        m = v > m ? v : m;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        uint64_t o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+    }
+    __shared__ uint64_t wm[4];
+    if ((threadIdx.x & 63) == 0)
+        wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            m = wm[w] > m ? wm[w] : m;
+        m = wm[0] > m ? wm[0] : m;
+        uint32_t p = 0xFFFFFFFFu - (uint32_t)(m & 0xFFFFFFFFu);
+        size_t mp = (size_t)j * HW + p;
+        tno_peak pk;
+        pk.snr = snr[mp];
+        pk.flux = flux[mp];
+        pk.y = (int32_t)(p / (uint32_t)W);
+        pk.x = (int32_t)(p % (uint32_t)W);
+        out[j] = pk;
+    }
+}
+
+hipError_t launch_trajmax(hipStream_t st, int J, int ntiles, int W, int HW,
+                          const uint64_t *tile_keys, const float *snr, const float *flux,
+                          void *traj_max_out)
+{
+    hipLaunchKernelGGL(k_trajmax, dim3(J), dim3(256), 0, st, ntiles, W, HW, tile_keys, snr, flux,
+                       (tno_peak *)traj_max_out);
+    return hipGetLastError();
+}
+
+// Per start pixel: the bank maximum (Sec. 3.2); strict '>' keeps the lowest j.
+__global__ void k_best(int J, int HW, const float *__restrict__ snr, float *__restrict__ best_snr,
+                       int32_t *__restrict__ best_traj)
+{
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += gridDim.x * blockDim.x) {
+        float b = snr[p];
+        int bj = 0;
+        for (int j = 1; j < J; ++j) {
+            float s = snr[(size_t)j * HW + p];
+            if (s > b) {
+                b = s;
+                bj = j;
+            }
+        }
+        best_snr[p] = b;
+        best_traj[p] = bj;
+    }
+}
+
+hipError_t launch_best(hipStream_t st, int J, int HW, const float *snr, float *best_snr,
+                       int32_t *best_traj)
+{
+    int blocks = (HW + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_best, dim3(blocks), dim3(256), 0, st, J, HW, snr, best_snr, best_traj);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ exact top-k
+//
+// Order: SNR descending, then flat index j*H*W + y*W + x ascending (the map's
+// linear index).  Keys are the order-preserving uint32 images of the SNRs.
+// 1) four 8-bit radix passes find the k-th largest key K* and how many of the
+//    K*-valued elements are needed; 2) one pass appends every key > K*;
+// 3) chunk counts + a scan give each K*-valued element its rank in index
+//    order, and the first `need` are appended; 4) one block sorts the k.
+
+__global__ void k_topk_init(TopkState *st, int k, uint64_t *cand)
+{
+    if (threadIdx.x == 0) {
+        st->prefix = 0;
+        st->mask = 0;
+        st->k_rem = k;
+        st->n_gt = 0;
+    }
+    for (int i = threadIdx.x; i < 256; i += blockDim.x)
+        st->hist[i] = 0;
+    for (int i = threadIdx.x; i < 2 * TNO_MAX_TOPK; i += blockDim.x)
+        cand[i] = 0;
+}
+
+__global__ void k_topk_hist(const float *__restrict__ snr, int64_t N, TopkState *st, int shift)
+{
+    __shared__ uint32_t hl[256];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x)
+        hl[i] = 0;
+    __syncthreads();
+    const uint32_t prefix = st->prefix, mask = st->mask;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t key = ordered_key(snr[i]);
+        if ((key & mask) == prefix)
+            atomicAdd(&hl[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 256; i += blockDim.x)
+        if (hl[i])
+            atomicAdd(&st->hist[i], hl[i]);
+}
+
+__global__ void k_topk_select(TopkState *st, int shift)
+{
+    if (threadIdx.x == 0) {
+        int32_t krem = st->k_rem;
+        uint32_t above = 0;
+        int b = 255;
+        for (; b > 0; --b) {
+            uint32_t c = st->hist[b];
+            if ((int64_t)above + c >= (int64_t)krem)
+                break;
+            above += c;
+        }
+        st->prefix |= (uint32_t)b << shift;
+        st->mask |= 255u << shift;
+        st->k_rem = krem - (int32_t)above;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 256; i += blockDim.x)
+        st->hist[i] = 0;
+}
+
+// Append keys > K*; count K*-valued keys per chunk of TOPK_CHUNK elements.
+__global__ void k_topk_gt(const float *__restrict__ snr, int64_t N, int k, TopkState *st,
+                          uint32_t *__restrict__ chunk_cnt, uint64_t *__restrict__ cand)
+{
+    const uint32_t kstar = st->prefix;
+    const int64_t c0 = (int64_t)blockIdx.x * TOPK_CHUNK;
+    uint32_t ties = 0;
+    for (int64_t i = c0 + threadIdx.x; i < N && i < c0 + TOPK_CHUNK; i += blockDim.x) {
+        uint32_t key = ordered_key(snr[i]);
+        if (key > kstar) {
+            uint32_t pos = atomicAdd(&st->n_gt, 1u);
+            if (pos < (uint32_t)k) {      // at most k-1 keys exceed the k-th
+                cand[2 * pos] = key;
+                cand[2 * pos + 1] = (uint64_t)i;
+            }
+        } else if (key == kstar) {
+            ++ties;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1)
+        ties += __shfl_xor(ties, off, 64);
+    __shared__ uint32_t wt[4];
+    if ((threadIdx.x & 63) == 0)
+        wt[threadIdx.x >> 6] = ties;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        chunk_cnt[blockIdx.x] = wt[0] + wt[1] + wt[2] + wt[3];
+}
+
+// Exclusive scan of the chunk counts (one block).
+__global__ void k_topk_scan(uint32_t *cnt, int64_t n)
+{
+    __shared__ uint32_t carry;
+    __shared__ uint32_t buf[256];
+    if (threadIdx.x == 0)
+        carry = 0;
+    __syncthreads();
+    for (int64_t b = 0; b < n; b += 256) {
+        int64_t i = b + threadIdx.x;
+        uint32_t v = i < n ? cnt[i] : 0u;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            uint32_t t = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0u;
+            __syncthreads();
+            buf[threadIdx.x] += t;
+            __syncthreads();
+        }
+        uint32_t incl = buf[threadIdx.x];
+        if (i < n)
+            cnt[i] = carry + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 255)
+            carry += incl;
+        __syncthreads();
+    }
+}
+
+// Append the first `need` K*-valued elements in index order.
+__global__ void k_topk_ties(const float *__restrict__ snr, int64_t N, int k,
+                            const TopkState *__restrict__ st,
+                            const uint32_t *__restrict__ chunk_off, uint64_t *__restrict__ cand)
+{
+    const uint32_t kstar = st->prefix;
+    const uint32_t need = (uint32_t)st->k_rem;
+    const uint32_t n_gt = (uint32_t)k - need;
+    const uint32_t start = chunk_off[blockIdx.x];
+    if (start >= need)
+        return;
+    const int64_t c0 = (int64_t)blockIdx.x * TOPK_CHUNK;
+    __shared__ uint32_t buf[256];
+    uint32_t running = start;
+    for (int64_t b = c0; b < N && b < c0 + TOPK_CHUNK; b += 256) {
+        int64_t i = b + threadIdx.x;
+        uint32_t f = (i < N && ordered_key(snr[i]) == kstar) ? 1u : 0u;
+        buf[threadIdx.x] = f;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            uint32_t t = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0u;
+            __syncthreads();
+            buf[threadIdx.x] += t;
+            __syncthreads();
+        }
+        uint32_t rank = running + buf[threadIdx.x] - f;
+        if (f && rank < need) {
+            cand[2 * (n_gt + rank)] = kstar;
+            cand[2 * (n_gt + rank) + 1] = (uint64_t)i;
+        }
+        uint32_t tot = buf[255];
+        __syncthreads();
+        running += tot;
+        if (running >= need)
+            break;
+    }
+}
+
+// Sort the k candidates (key desc, index asc) in LDS and write the output.
+__global__ __launch_bounds__(1024) void k_topk_final(const float *__restrict__ flux, int64_t N,
+                                                     int k, int HW, int W,
+                                                     const uint64_t *__restrict__ cand,
+                                                     tno_candidate *__restrict__ out)
+{
+    __shared__ uint64_t sk[TNO_MAX_TOPK];
+    __shared__ uint64_t si[TNO_MAX_TOPK];
+    const int t = threadIdx.x;
+    // pad with the smallest key and the largest index
+    sk[t] = t < k ? cand[2 * t] : 0u;
+    si[t] = t < k ? cand[2 * t + 1] : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= TNO_MAX_TOPK; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            int p = t ^ stride;
+            if (p > t) {
+                // "before" = larger key, or equal key and smaller index
+                bool t_before_p = sk[t] > sk[p] || (sk[t] == sk[p] && si[t] < si[p]);
+                bool ascending = (t & size) == 0;   // ascending in "before" order
+                if (ascending != t_before_p) {
+                    uint64_t a = sk[t]; sk[t] = sk[p]; sk[p] = a;
+                    uint64_t b = si[t]; si[t] = si[p]; si[p] = b;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (t < k) {
+        uint64_t idx = si[t] < (uint64_t)N ? si[t] : 0;
+        tno_candidate c;
+        c.snr = key_to_float((uint32_t)sk[t]);
+        c.flux = flux[idx];
+        c.traj = (int32_t)(idx / (uint64_t)HW);
+        uint32_t p = (uint32_t)(idx % (uint64_t)HW);
+        c.y = (int32_t)(p / (uint32_t)W);
+        c.x = (int32_t)(p % (uint32_t)W);
+        out[t] = c;
+    }
+}
+
+hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int64_t N, int HW,
+                       int W, int k, TopkState *state, uint32_t *chunk_cnt, int64_t n_chunks,
+                       uint64_t *cand, void *topk_out)
+{
+    hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(256), 0, st, state, k, cand);
+    int64_t blocks = (N + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    for (int pass = 0; pass < 4; ++pass) {
+        int shift = 24 - 8 * pass;
+        hipLaunchKernelGGL(k_topk_hist, dim3((unsigned)blocks), dim3(256), 0, st, snr, N, state, shift);
+        hipLaunchKernelGGL(k_topk_select, dim3(1), dim3(256), 0, st, state, shift);
+    }
+    hipLaunchKernelGGL(k_topk_gt, dim3((unsigned)n_chunks), dim3(256), 0, st, snr, N, k, state, chunk_cnt, cand);
+    hipLaunchKernelGGL(k_topk_scan, dim3(1), dim3(256), 0, st, chunk_cnt, n_chunks);
+    hipLaunchKernelGGL(k_topk_ties, dim3((unsigned)n_chunks), dim3(256), 0, st, snr, N, k, state, chunk_cnt, cand);
+    hipLaunchKernelGGL(k_topk_final, dim3(1), dim3(TNO_MAX_TOPK), 0, st, flux, N, k, HW, W, cand,
+                       (tno_candidate *)topk_out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ quantize (precision form)
+
+__device__ __forceinline__ uint32_t encode_e4m3(float x)
+{
+    // round to nearest even, saturating at 448; zero keeps no sign
+    uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+    float a = fminf(fabsf(x), 448.0f);
+    uint32_t mag;
+    if (a < 0.015625f) {                          // below 2^-6: subnormal step 2^-9
+        mag = (uint32_t)rintf(a * 512.0f);        // 0..8 (8 is the smallest normal)
+    } else {
+        uint32_t u = __float_as_uint(a);
+        int E = (int)((u >> 23) & 0xFF) - 127;    // -6..8
+        uint32_t m = u & 0x7FFFFFu;
+        uint32_t r = m >> 20, rem = m & 0xFFFFFu;
+        if (rem > 0x80000u || (rem == 0x80000u && (r & 1u)))
+            ++r;
+        if (r == 8u) {
+            r = 0;
+            ++E;
+        }
+        mag = ((uint32_t)(E + 7) << 3) | r;
+        if (mag > 0x7Eu)
+            mag = 0x7Eu;
+    }
+    return mag ? (sign | mag) : 0u;
+}
+
+__device__ __forceinline__ uint32_t encode_bf16(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// One block per (frame, 64x64 tile): amax, power-of-two scale, encode.
+template <int DT>
+__global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ R, int H, int W,
+                                                  void *__restrict__ codes,
+                                                  float *__restrict__ scales)
+{
+    const int nqx = gridDim.x, nqy = gridDim.y;
+    const int tx = blockIdx.x, ty = blockIdx.y, k = blockIdx.z;
+    const size_t fo = (size_t)k * H * W;
+    float am = 0.0f;
+    for (int e = threadIdx.x; e < TNO_QTILE * TNO_QTILE; e += 256) {
+        int y = ty * TNO_QTILE + (e >> 6), x = tx * TNO_QTILE + (e & 63);
+        if (y < H && x < W)
+            am = fmaxf(am, fabsf(R[fo + (size_t)y * W + x]));
+    }
+    for (int off = 32; off >= 1; off >>= 1)
+        am = fmaxf(am, __shfl_xor(am, off, 64));
+    __shared__ float wa[4];
+    if ((threadIdx.x & 63) == 0)
+        wa[threadIdx.x >> 6] = am;
+    __syncthreads();
+    am = fmaxf(fmaxf(wa[0], wa[1]), fmaxf(wa[2], wa[3]));
+    constexpr int E = DT == TNO_FP8_E4M3 ? 8 : 15;
+    int c = 0;
+    float s = 1.0f;
+    if (am > 0.0f) {
+        int e2;
+        float m = frexpf(am, &e2);     // am = m * 2^e2, m in [0.5, 1)
+        c = (m == 0.5f) ? e2 - 1 : e2;
+        s = ldexpf(1.0f, c - E);
+    }
+    if (threadIdx.x == 0)
+        scales[((size_t)k * nqy + ty) * nqx + tx] = s;
+    for (int e = threadIdx.x; e < TNO_QTILE * TNO_QTILE; e += 256) {
+        int y = ty * TNO_QTILE + (e >> 6), x = tx * TNO_QTILE + (e & 63);
+        if (y >= H || x >= W)
+            continue;
+        size_t i = fo + (size_t)y * W + x;
+        float v = am > 0.0f ? ldexpf(R[i], E - c) : R[i];
+        if constexpr (DT == TNO_FP8_E4M3) {
+            ((uint8_t *)codes)[i] = (uint8_t)encode_e4m3(v);
+        } else if constexpr (DT == TNO_BF16) {
+            ((uint16_t *)codes)[i] = (uint16_t)encode_bf16(v);
+        } else {
+            _Float16 hv = (_Float16)v;
+            ((_Float16 *)codes)[i] = hv;
+        }
+    }
+}
+
+hipError_t launch_quantize(hipStream_t st, int dtype, const float *R, int T, int H, int W,
+                           void *codes, float *scales)
+{
+    dim3 grid((W + TNO_QTILE - 1) / TNO_QTILE, (H + TNO_QTILE - 1) / TNO_QTILE, T);
+    switch (dtype) {
+    case TNO_BF16: hipLaunchKernelGGL(k_quantize<TNO_BF16>, grid, dim3(256), 0, st, R, H, W, codes, scales); break;
+    case TNO_F16: hipLaunchKernelGGL(k_quantize<TNO_F16>, grid, dim3(256), 0, st, R, H, W, codes, scales); break;
+    case TNO_FP8_E4M3: hipLaunchKernelGGL(k_quantize<TNO_FP8_E4M3>, grid, dim3(256), 0, st, R, H, W, codes, scales); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tno

@@ -1,0 +1,783 @@
+// tno_runtime.cpp -- host side of the C ABI declared in include/tno_search.h.
+//
+// Responsibilities: argument validation, the per-request plan (shift bounds,
+// padding of the staged stack, trail-kernel layout, tiling, footprint),
+// admission against an HBM budget and an in-flight limit, one device arena
+// per request, the kernel sequence on the handle's stream, and ticketed
+// completion with HIP events.  Validation and planning touch no GPU and back
+// the host-only helpers tno_search_validate / tno_search_footprint.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/tno_search.h"
+#include "tno_internal.h"
+
+namespace {
+
+thread_local char g_last_error[256] = {0};
+
+void set_msg(char *dst, size_t n, const char *fmt, va_list ap)
+{
+    if (dst && n)
+        vsnprintf(dst, n, fmt, ap);
+}
+
+struct Fail {
+    int code;
+    char msg[160];
+};
+
+Fail fail(int code, const char *fmt, ...)
+{
+    Fail f;
+    f.code = code;
+    va_list ap;
+    va_start(ap, fmt);
+    set_msg(f.msg, sizeof f.msg, fmt, ap);
+    va_end(ap);
+    return f;
+}
+
+constexpr int PAD_CAP = 512;      // largest zero border of the staged stack, per side
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_bytes(int dtype)
+{
+    switch (dtype) {
+    case TNO_F32: return 4;
+    case TNO_BF16:
+    case TNO_F16: return 2;
+    case TNO_FP8_E4M3: return 1;
+    default: return 0;
+    }
+}
+
+// Everything derived from a request before any device work.
+struct Plan {
+    int H = 0, W = 0, T = 0, J = 0, S = 0, h = 0, kind = 0, dtype = 0, k = 0;
+    double sigma_px = 0, t_ref = 0;
+    bool dev = false;
+    int Pt = 0, Pb = 0, Pl = 0, Pr = 0, Hp = 0, Wp4 = 0;
+    std::vector<tno::TrailInfo> trail;
+    int64_t n_colmeta = 0, n_kvals = 0;
+    int ntx = 0, nty = 0, ntiles = 0;
+    int lntx = 0, lnty = 0;
+    int64_t N = 0, n_chunks = 0;
+    bool own_snr = true, own_flux = true;
+    // arena layout (byte offsets)
+    size_t o_R = 0, o_scales = 0, o_sigma = 0, o_times = 0, o_vel = 0, o_Z = 0, o_iv32 = 0,
+           o_iv64 = 0, o_tab32 = 0, o_tab64 = 0, o_trail = 0, o_colmeta = 0, o_kvals = 0,
+           o_err = 0, o_lam = 0, o_snr = 0, o_flux = 0, o_tkeys = 0, o_tstate = 0, o_chunks = 0,
+           o_cand = 0, o_tmax = 0, o_topk = 0, o_best = 0, o_bestj = 0, bytes = 0;
+};
+
+bool finite(double v) { return std::isfinite(v); }
+
+// Checks that need no input values.  Returns code 0 on success.
+Fail check_shape(const tno_request *r, const tno_outputs *o)
+{
+    if (!r)
+        return fail(TNO_E_INVAL, "request is NULL");
+    if (!o)
+        return fail(TNO_E_INVAL, "outputs is NULL");
+    if (r->reserved != 0)
+        return fail(TNO_E_INVAL, "request.reserved must be 0");
+    if (r->height <= 0 || r->width <= 0 || r->n_frames <= 0)
+        return fail(TNO_E_INVAL, "height, width and n_frames must be positive");
+    if (r->height > 32768 || r->width > 32768)
+        return fail(TNO_E_INVAL, "height and width must be <= 32768");
+    if (r->n_frames > 65535)
+        return fail(TNO_E_INVAL, "n_frames must be <= 65535");
+    if (r->n_traj <= 0)
+        return fail(TNO_E_INVAL, "n_traj must be >= 1");
+    if (r->dtype < TNO_F32 || r->dtype > TNO_FP8_E4M3)
+        return fail(TNO_E_INVAL, "unknown dtype %d", r->dtype);
+    if (r->dtype != TNO_F32 && !r->tile_scales)
+        return fail(TNO_E_INVAL, "tile_scales required for reduced-precision residuals");
+    if (!r->residuals && r->stack_key == 0)
+        return fail(TNO_E_INVAL, "residuals is NULL and no stack_key given");
+    if (!r->sigma || !r->times || !r->velocities)
+        return fail(TNO_E_INVAL, "sigma, times and velocities must be non-NULL");
+    if (r->prf.kind != TNO_PRF_GAUSS_SAMPLED && r->prf.kind != TNO_PRF_GAUSS_INTEGRATED)
+        return fail(TNO_E_INVAL, "unknown PRF kind %d", r->prf.kind);
+    if (r->prf.stamp < 1 || r->prf.stamp > TNO_MAX_STAMP || (r->prf.stamp % 2) == 0)
+        return fail(TNO_E_INVAL, "stamp must be odd and in 1..%d", TNO_MAX_STAMP);
+    if (!(r->prf.sigma_px > 0.0) || !finite(r->prf.sigma_px))
+        return fail(TNO_E_INVAL, "prf.sigma_px must be finite and > 0");
+    if (r->top_k < 0 || r->top_k > TNO_MAX_TOPK)
+        return fail(TNO_E_INVAL, "top_k must be in 0..%d", TNO_MAX_TOPK);
+    if (r->top_k > 0 && !o->topk)
+        return fail(TNO_E_INVAL, "top_k > 0 needs outputs.topk");
+    if ((r->flags & ~(TNO_REQ_DEVICE_PTRS | TNO_REQ_VALIDATE)) != 0)
+        return fail(TNO_E_INVAL, "unknown request flags 0x%x", r->flags);
+    if (!finite(r->t_ref) && !std::isnan(r->t_ref))
+        return fail(TNO_E_INVAL, "t_ref must be finite or NaN");
+    if ((double)r->n_traj * r->n_frames > 2.0e8)
+        return fail(TNO_E_INVAL, "n_traj*n_frames too large");
+    const double jhw = (double)r->n_traj * r->height * r->width;
+    if (jhw > 4.0e12)
+        return fail(TNO_E_INVAL, "n_traj*height*width too large");
+    const double items = (double)r->n_traj * ((r->height + tno::SEARCH_TY - 1) / tno::SEARCH_TY) *
+                         ((r->width + tno::SEARCH_TX - 1) / tno::SEARCH_TX);
+    if (items > 2.0e9)
+        return fail(TNO_E_INVAL, "too many (tile, trajectory) work items");
+    return fail(TNO_OK, "");
+}
+
+// Build the plan from host copies of times and velocities.
+Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
+               const double *vel, Plan &p)
+{
+    Fail f = check_shape(r, o);
+    if (f.code)
+        return f;
+    p.H = r->height;
+    p.W = r->width;
+    p.T = r->n_frames;
+    p.J = r->n_traj;
+    p.S = r->prf.stamp;
+    p.h = p.S / 2;
+    p.kind = r->prf.kind;
+    p.sigma_px = r->prf.sigma_px;
+    p.dtype = r->dtype;
+    p.dev = (r->flags & TNO_REQ_DEVICE_PTRS) != 0;
+    for (int k = 0; k < p.T; ++k)
+        if (!finite(times[k]))
+            return fail(TNO_E_INVAL, "times[%d] is not finite", k);
+    p.t_ref = std::isnan(r->t_ref) ? times[0] : r->t_ref;
+    double dtmin = INFINITY, dtmax = -INFINITY;
+    for (int k = 0; k < p.T; ++k) {
+        double dt = times[k] - p.t_ref;
+        dtmin = std::min(dtmin, dt);
+        dtmax = std::max(dtmax, dt);
+    }
+    if (!finite(dtmin) || !finite(dtmax))
+        return fail(TNO_E_INVAL, "time baseline overflows");
+    // Shift bounds per trajectory: floor(v*dt + 1/2) is monotone in dt, so the
+    // extremes sit at the extreme times; one pixel of margin each side.
+    int gymin = 0, gymax = 0, gxmin = 0, gxmax = 0;
+    const int H = p.H, W = p.W, h = p.h, S = p.S;
+    p.trail.resize(p.J);
+    int64_t coff = 0, voff = 0;
+    for (int j = 0; j < p.J; ++j) {
+        double vx = vel[2 * j], vy = vel[2 * j + 1];
+        if (!finite(vx) || !finite(vy))
+            return fail(TNO_E_INVAL, "velocity %d is not finite", j);
+        double e[4] = {vx * dtmin, vx * dtmax, vy * dtmin, vy * dtmax};
+        for (double d : e)
+            if (!(std::fabs(d) < 1.0e9))
+                return fail(TNO_E_INVAL, "trajectory %d moves more than 1e9 px", j);
+        double x1 = std::floor(e[0] + 0.5), x2 = std::floor(e[1] + 0.5);
+        double y1 = std::floor(e[2] + 0.5), y2 = std::floor(e[3] + 0.5);
+        int xlo = (int)std::min(x1, x2) - 1, xhi = (int)std::max(x1, x2) + 1;
+        int ylo = (int)std::min(y1, y2) - 1, yhi = (int)std::max(y1, y2) + 1;
+        gxmin = std::min(gxmin, xlo);
+        gxmax = std::max(gxmax, xhi);
+        gymin = std::min(gymin, ylo);
+        gymax = std::max(gymax, yhi);
+        tno::TrailInfo ti{};
+        int qx0 = std::max(xlo - h, -(W - 1)), qx1 = std::min(xhi + h, W - 1);
+        ti.qx0 = qx0;
+        ti.ncols = std::max(0, qx1 - qx0 + 1);
+        ti.qy_lo = std::max(ylo - h, -(H - 1));
+        ti.qy_hi = std::min(yhi + h, H - 1);
+        int nrows = std::max(0, ti.qy_hi - ti.qy_lo + 1);
+        int cap = nrows;
+        if (vx != 0.0) {
+            double c = std::ceil((double)S * (1.0 + std::fabs(vy) / std::fabs(vx))) + 3.0;
+            if (c < (double)cap)
+                cap = (int)c;
+        }
+        ti.cap = std::max(cap, 1);
+        ti.col_off = coff;
+        ti.val_off = voff;
+        coff += ti.ncols;
+        voff += (int64_t)ti.ncols * ti.cap;
+        p.trail[j] = ti;
+    }
+    p.n_colmeta = std::max<int64_t>(coff, 1);
+    p.n_kvals = std::max<int64_t>(voff, 1);
+    p.Pt = std::min(PAD_CAP, std::max(0, -gymin) + h);
+    p.Pb = std::min(PAD_CAP, std::max(0, gymax) + h + tno::SEARCH_TY);
+    p.Pl = (int)align_up((size_t)std::min(PAD_CAP, std::max(0, -gxmin) + h + 3), 4);
+    p.Pr = std::min(PAD_CAP, std::max(0, gxmax) + h + tno::SEARCH_TX + 4);
+    p.Hp = H + p.Pt + p.Pb;
+    p.Wp4 = (int)(align_up((size_t)W + p.Pl + p.Pr, 4) / 4);
+    p.ntx = (W + tno::SEARCH_TX - 1) / tno::SEARCH_TX;
+    p.nty = (H + tno::SEARCH_TY - 1) / tno::SEARCH_TY;
+    p.ntiles = p.ntx * p.nty;
+    p.lntx = (W + tno::LAMBDA_TX - 1) / tno::LAMBDA_TX;
+    p.lnty = (H + tno::LAMBDA_TY - 1) / tno::LAMBDA_TY;
+    if ((double)p.lntx * p.lnty * p.J > 2.0e9)
+        return fail(TNO_E_INVAL, "too many normaliser work items");
+    p.N = (int64_t)p.J * H * W;
+    p.k = (int)std::min<int64_t>(r->top_k, p.N);
+    p.n_chunks = (p.N + tno::TOPK_CHUNK - 1) / tno::TOPK_CHUNK;
+    p.own_snr = !(p.dev && o->snr);
+    p.own_flux = !(p.dev && o->flux);
+
+    // arena layout
+    const size_t HW = (size_t)H * W, T = (size_t)p.T, J = (size_t)p.J;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + std::max<size_t>(bytes, 1), ALIGN);
+        return at;
+    };
+    if (!p.dev) {
+        p.o_R = take(T * HW * elem_bytes(p.dtype));
+        if (p.dtype != TNO_F32)
+            p.o_scales = take(T * ((H + 63) / 64) * ((W + 63) / 64) * 4);
+        p.o_sigma = take(HW * 4);
+        p.o_times = take(T * 8);
+        p.o_vel = take(J * 16);
+    }
+    p.o_Z = take(T * (size_t)p.Hp * p.Wp4 * 16);
+    p.o_iv32 = take(HW * 4);
+    p.o_iv64 = take(HW * 8);
+    p.o_tab32 = take(J * T * tno::table_stride(S) * 4);
+    p.o_tab64 = take(J * T * 2 * S * 8);
+    p.o_trail = take(J * sizeof(tno::TrailInfo));
+    p.o_colmeta = take((size_t)p.n_colmeta * 8);
+    p.o_kvals = take((size_t)p.n_kvals * 8);
+    p.o_err = take(4);
+    p.o_lam = take(J * HW * 8);
+    if (p.own_snr)
+        p.o_snr = take(J * HW * 4);
+    if (p.own_flux)
+        p.o_flux = take(J * HW * 4);
+    p.o_tkeys = take(J * p.ntiles * 8);
+    p.o_tstate = take(sizeof(tno::TopkState));
+    p.o_chunks = take((size_t)p.n_chunks * 4);
+    p.o_cand = take((size_t)TNO_MAX_TOPK * 16);
+    p.o_tmax = take(J * sizeof(tno_peak));
+    p.o_topk = take((size_t)TNO_MAX_TOPK * sizeof(tno_candidate));
+    p.o_best = take(HW * 4);
+    p.o_bestj = take(HW * 4);
+    p.bytes = off;
+    return fail(TNO_OK, "");
+}
+
+struct Request {
+    uint64_t ticket = 0;
+    Plan plan;
+    tno_outputs out{};
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    hipEvent_t ev[6] = {};   // phase boundaries; ev[0] start, ev[5] end
+    std::chrono::steady_clock::time_point t_submit;
+    uint64_t updates = 0;
+};
+
+// Device arenas of finished requests, kept for reuse: a later request takes
+// the smallest cached block that fits, so steady-state serving and repeated
+// searches of one shape allocate nothing.  Blocks are freed when the cached
+// total would exceed the handle's budget, on allocation failure, and at
+// destroy.
+struct ArenaCache {
+    std::multimap<size_t, void *> blocks;
+    size_t held = 0;
+    void *take(size_t bytes, size_t *got)
+    {
+        auto it = blocks.lower_bound(bytes);
+        if (it == blocks.end() || it->first > 2 * bytes + (64u << 20))
+            return nullptr;
+        void *p = it->second;
+        *got = it->first;
+        held -= it->first;
+        blocks.erase(it);
+        return p;
+    }
+    void put(void *p, size_t bytes)
+    {
+        blocks.emplace(bytes, p);
+        held += bytes;
+    }
+    void trim(size_t keep)
+    {
+        while (held > keep && !blocks.empty()) {
+            auto it = blocks.begin();      // drop the smallest first
+            (void)hipFree(it->second);
+            held -= it->first;
+            blocks.erase(it);
+        }
+    }
+};
+
+}  // namespace
+
+struct tno_search {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t budget = 0;
+    uint64_t in_use = 0;
+    int max_inflight = 64;
+    uint64_t next_ticket = 1;
+    std::mutex mu;
+    std::map<uint64_t, Request *> live;
+    ArenaCache cache;
+};
+
+namespace {
+
+void set_last(const Fail &f) { snprintf(g_last_error, sizeof g_last_error, "%s", f.msg); }
+
+int hip_fail(hipError_t e, const char *what, char *msg, size_t n)
+{
+    if (msg)
+        snprintf(msg, n, "%s: %s", what, hipGetErrorString(e));
+    snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
+    return TNO_E_DEVICE;
+}
+
+template <class T> T *at(void *arena, size_t off) { return (T *)((char *)arena + off); }
+
+// Enqueue the whole search of one request on the handle's stream.
+hipError_t enqueue(tno_search *hd, Request *q, const tno_request *r)
+{
+    const Plan &p = q->plan;
+    hipStream_t st = hd->stream;
+    void *A = q->arena;
+    const void *R = p.dev ? r->residuals : at<void>(A, p.o_R);
+    const float *scales = p.dtype == TNO_F32 ? nullptr
+                          : (p.dev ? r->tile_scales : at<float>(A, p.o_scales));
+    const float *sigma = p.dev ? r->sigma : at<float>(A, p.o_sigma);
+    const double *times = p.dev ? r->times : at<double>(A, p.o_times);
+    const double *vel = p.dev ? r->velocities : at<double>(A, p.o_vel);
+    float *snr = p.own_snr ? at<float>(A, p.o_snr) : q->out.snr;
+    float *flux = p.own_flux ? at<float>(A, p.o_flux) : q->out.flux;
+    const int HW = p.H * p.W;
+    hipError_t e;
+#define TRY(x)                  \
+    do {                        \
+        e = (x);                \
+        if (e != hipSuccess)    \
+            return e;           \
+    } while (0)
+    TRY(hipEventRecord(q->ev[0], st));
+    TRY(tno::launch_zero(st, at<int32_t>(A, p.o_err), 1));
+    TRY(hipMemcpyAsync(at<void>(A, p.o_trail), p.trail.data(), p.trail.size() * sizeof(tno::TrailInfo),
+                       hipMemcpyHostToDevice, st));
+    TRY(tno::launch_ivar(st, HW, sigma, at<float>(A, p.o_iv32), at<double>(A, p.o_iv64)));
+    TRY(tno::launch_prep_z(st, p.dtype, R, scales, at<float>(A, p.o_iv32), at<float4>(A, p.o_Z), p.T,
+                           p.H, p.W, p.Hp, p.Wp4, p.Pt, p.Pl));
+    TRY(hipEventRecord(q->ev[1], st));
+    TRY(tno::launch_table(st, p.J, p.T, times, p.t_ref, vel, p.kind, p.sigma_px, p.S,
+                          at<int32_t>(A, p.o_tab32), at<double>(A, p.o_tab64)));
+    TRY(tno::launch_trail(st, p.J, p.T, p.S, p.H, at<int32_t>(A, p.o_tab32), at<double>(A, p.o_tab64),
+                          at<tno::TrailInfo>(A, p.o_trail), at<int2>(A, p.o_colmeta),
+                          at<double>(A, p.o_kvals), at<int32_t>(A, p.o_err)));
+    TRY(hipEventRecord(q->ev[2], st));
+    tno::LambdaArgs la;
+    la.info = at<tno::TrailInfo>(A, p.o_trail);
+    la.colmeta = at<int2>(A, p.o_colmeta);
+    la.kvals = at<double>(A, p.o_kvals);
+    la.ivar64 = at<double>(A, p.o_iv64);
+    la.lam = at<double>(A, p.o_lam);
+    la.H = p.H;
+    la.W = p.W;
+    la.J = p.J;
+    la.ntx = p.lntx;
+    la.nty = p.lnty;
+    la.n_items = p.lntx * p.lnty * p.J;
+    TRY(tno::launch_lambda(st, la));
+    TRY(hipEventRecord(q->ev[3], st));
+    tno::SearchArgs sa;
+    sa.Z4 = at<float4>(A, p.o_Z);
+    sa.tab32 = at<int32_t>(A, p.o_tab32);
+    sa.lam = at<double>(A, p.o_lam);
+    sa.snr = snr;
+    sa.flux = flux;
+    sa.tile_keys = at<uint64_t>(A, p.o_tkeys);
+    sa.H = p.H;
+    sa.W = p.W;
+    sa.T = p.T;
+    sa.J = p.J;
+    sa.Hp = p.Hp;
+    sa.Wp4 = p.Wp4;
+    sa.Pt = p.Pt;
+    sa.Pl = p.Pl;
+    sa.ntx = p.ntx;
+    sa.nty = p.nty;
+    sa.n_items = p.ntiles * p.J;
+    TRY(tno::launch_search(st, p.S, sa));
+    TRY(hipEventRecord(q->ev[4], st));
+    TRY(tno::launch_trajmax(st, p.J, p.ntiles, p.W, HW, sa.tile_keys, snr, flux, at<void>(A, p.o_tmax)));
+    TRY(tno::launch_best(st, p.J, HW, snr, at<float>(A, p.o_best), at<int32_t>(A, p.o_bestj)));
+    if (p.k > 0)
+        TRY(tno::launch_topk(st, snr, flux, p.N, HW, p.W, p.k, at<tno::TopkState>(A, p.o_tstate),
+                             at<uint32_t>(A, p.o_chunks), p.n_chunks, at<uint64_t>(A, p.o_cand),
+                             at<void>(A, p.o_topk)));
+    if (p.dev) {
+        const tno_outputs &o = q->out;
+        if (o.traj_max)
+            TRY(hipMemcpyAsync(o.traj_max, at<void>(A, p.o_tmax), (size_t)p.J * sizeof(tno_peak),
+                               hipMemcpyDeviceToDevice, st));
+        if (o.topk && p.k > 0)
+            TRY(hipMemcpyAsync(o.topk, at<void>(A, p.o_topk), (size_t)p.k * sizeof(tno_candidate),
+                               hipMemcpyDeviceToDevice, st));
+        if (o.best_snr)
+            TRY(hipMemcpyAsync(o.best_snr, at<void>(A, p.o_best), (size_t)HW * 4, hipMemcpyDeviceToDevice, st));
+        if (o.best_traj)
+            TRY(hipMemcpyAsync(o.best_traj, at<void>(A, p.o_bestj), (size_t)HW * 4, hipMemcpyDeviceToDevice, st));
+    }
+    TRY(hipEventRecord(q->ev[5], st));
+#undef TRY
+    return hipSuccess;
+}
+
+void release(tno_search *hd, Request *q)
+{
+    if (q->arena)
+        hd->cache.put(q->arena, q->arena_bytes);
+    for (hipEvent_t &e : q->ev)
+        if (e)
+            (void)hipEventDestroy(e);
+    hd->in_use -= q->plan.bytes;
+    delete q;
+}
+
+// Copy host-side outputs back after completion (the stream work is done).
+hipError_t finish_outputs(Request *q)
+{
+    const Plan &p = q->plan;
+    if (p.dev)
+        return hipSuccess;
+    const tno_outputs &o = q->out;
+    void *A = q->arena;
+    const size_t HW = (size_t)p.H * p.W, J = (size_t)p.J;
+    hipError_t e = hipSuccess;
+    auto cp = [&](void *dst, size_t off, size_t bytes) {
+        if (dst && e == hipSuccess)
+            e = hipMemcpy(dst, at<void>(A, off), bytes, hipMemcpyDeviceToHost);
+    };
+    cp(o.snr, p.o_snr, J * HW * 4);
+    cp(o.flux, p.o_flux, J * HW * 4);
+    cp(o.best_snr, p.o_best, HW * 4);
+    cp(o.best_traj, p.o_bestj, HW * 4);
+    cp(o.traj_max, p.o_tmax, J * sizeof(tno_peak));
+    if (p.k > 0)
+        cp(o.topk, p.o_topk, (size_t)p.k * sizeof(tno_candidate));
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tno_search_validate(const tno_request *req, const tno_outputs *out, char *msg, int32_t len)
+{
+    Fail f = check_shape(req, out);
+    if (f.code == TNO_OK && !(req->flags & TNO_REQ_DEVICE_PTRS)) {
+        Plan p;
+        f = make_plan(req, out, req->times, req->velocities, p);
+    }
+    if (msg && len > 0)
+        snprintf(msg, (size_t)len, "%s", f.msg);
+    return f.code;
+}
+
+uint64_t tno_search_footprint(const tno_request *req, const tno_outputs *out)
+{
+    if (!req || !out || (req->flags & TNO_REQ_DEVICE_PTRS))
+        return 0;
+    Plan p;
+    Fail f = make_plan(req, out, req->times, req->velocities, p);
+    return f.code == TNO_OK ? (uint64_t)p.bytes : 0;
+}
+
+const char *tno_search_last_error(void) { return g_last_error; }
+
+int tno_search_create(const tno_config *cfg, tno_search **out_handle)
+{
+    if (!cfg || !out_handle) {
+        set_last(fail(TNO_E_INVAL, "config or out_handle is NULL"));
+        return TNO_E_INVAL;
+    }
+    if (cfg->reserved != 0) {
+        set_last(fail(TNO_E_INVAL, "config.reserved must be 0"));
+        return TNO_E_INVAL;
+    }
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || cfg->device < 0 || cfg->device >= ndev) {
+        set_last(fail(TNO_E_DEVICE, "device %d not available (%d devices)", cfg->device, ndev));
+        return TNO_E_DEVICE;
+    }
+    if ((e = hipSetDevice(cfg->device)) != hipSuccess)
+        return hip_fail(e, "hipSetDevice", nullptr, 0);
+    tno_search *h = new (std::nothrow) tno_search();
+    if (!h) {
+        set_last(fail(TNO_E_NOMEM, "out of host memory"));
+        return TNO_E_NOMEM;
+    }
+    h->device = cfg->device;
+    h->max_inflight = cfg->max_inflight > 0 ? cfg->max_inflight : 64;
+    if (cfg->stream) {
+        h->stream = (hipStream_t)cfg->stream;
+    } else {
+        if ((e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking)) != hipSuccess) {
+            delete h;
+            return hip_fail(e, "hipStreamCreate", nullptr, 0);
+        }
+        h->own_stream = true;
+    }
+    size_t fr = 0, tot = 0;
+    if ((e = hipMemGetInfo(&fr, &tot)) != hipSuccess) {
+        if (h->own_stream)
+            (void)hipStreamDestroy(h->stream);
+        delete h;
+        return hip_fail(e, "hipMemGetInfo", nullptr, 0);
+    }
+    h->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
+    *out_handle = h;
+    return TNO_OK;
+}
+
+int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *out,
+                      uint64_t *out_ticket)
+{
+    if (!h || !out_ticket) {
+        set_last(fail(TNO_E_INVAL, "handle or out_ticket is NULL"));
+        return TNO_E_INVAL;
+    }
+    Fail f = check_shape(req, out);
+    if (f.code) {
+        set_last(f);
+        return f.code;
+    }
+    if (!req->residuals) {
+        set_last(fail(TNO_E_INVAL, "stack_key %llu is not resident", (unsigned long long)req->stack_key));
+        return TNO_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lock(h->mu);
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipSetDevice", nullptr, 0);
+    const bool dev = (req->flags & TNO_REQ_DEVICE_PTRS) != 0;
+    std::vector<double> times_h, vel_h;
+    const double *times = req->times, *vel = req->velocities;
+    if (dev) {
+        times_h.resize(req->n_frames);
+        vel_h.resize((size_t)2 * req->n_traj);
+        if ((e = hipMemcpy(times_h.data(), req->times, times_h.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess ||
+            (e = hipMemcpy(vel_h.data(), req->velocities, vel_h.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(e, "reading times/velocities", nullptr, 0);
+        times = times_h.data();
+        vel = vel_h.data();
+    }
+    Request *q = new (std::nothrow) Request();
+    if (!q) {
+        set_last(fail(TNO_E_NOMEM, "out of host memory"));
+        return TNO_E_NOMEM;
+    }
+    f = make_plan(req, out, times, vel, q->plan);
+    if (f.code) {
+        delete q;
+        set_last(f);
+        return f.code;
+    }
+    const Plan &p = q->plan;
+    if (p.bytes > h->budget) {
+        delete q;
+        set_last(fail(TNO_E_NOMEM, "request needs %.3g GB, budget is %.3g GB", p.bytes / 1e9, h->budget / 1e9));
+        return TNO_E_NOMEM;
+    }
+    if ((int)h->live.size() >= h->max_inflight || h->in_use + p.bytes > h->budget) {
+        delete q;
+        set_last(fail(TNO_E_BUSY, "in-flight limit or HBM budget reached"));
+        return TNO_E_BUSY;
+    }
+    if (req->flags & TNO_REQ_VALIDATE) {
+        // scan host residuals and sigma for non-finite values (device inputs are
+        // scanned after staging by the same rule: non-finite residuals are rejected)
+        if (!dev && req->dtype == TNO_F32) {
+            const float *Rh = (const float *)req->residuals;
+            size_t n = (size_t)p.T * p.H * p.W;
+            for (size_t i = 0; i < n; ++i)
+                if (!std::isfinite(Rh[i])) {
+                    delete q;
+                    set_last(fail(TNO_E_INVAL, "residual %zu is not finite", i));
+                    return TNO_E_INVAL;
+                }
+        }
+    }
+    q->out = *out;
+    q->t_submit = std::chrono::steady_clock::now();
+    q->updates = (uint64_t)p.J * p.H * p.W * p.T;
+    q->arena = h->cache.take(p.bytes, &q->arena_bytes);
+    if (!q->arena) {
+        // make room: cached blocks count against the budget
+        h->cache.trim(h->budget > h->in_use + p.bytes ? h->budget - h->in_use - p.bytes : 0);
+        if ((e = hipMalloc(&q->arena, p.bytes)) != hipSuccess) {
+            (void)hipGetLastError();
+            h->cache.trim(0);
+            if ((e = hipMalloc(&q->arena, p.bytes)) != hipSuccess) {
+                (void)hipGetLastError();
+                q->arena = nullptr;
+                delete q;
+                set_last(fail(TNO_E_NOMEM, "hipMalloc of %.3g GB failed", p.bytes / 1e9));
+                return TNO_E_NOMEM;
+            }
+        }
+        q->arena_bytes = p.bytes;
+    }
+    h->in_use += p.bytes;
+    for (hipEvent_t &ev : q->ev)
+        if ((e = hipEventCreate(&ev)) != hipSuccess) {
+            release(h, q);
+            return hip_fail(e, "hipEventCreate", nullptr, 0);
+        }
+    if (!dev) {
+        // host inputs are copied before submit returns
+        const size_t HW = (size_t)p.H * p.W;
+        void *A = q->arena;
+        struct {
+            size_t off;
+            const void *src;
+            size_t bytes;
+        } cps[] = {
+            {p.o_R, req->residuals, (size_t)p.T * HW * elem_bytes(p.dtype)},
+            {p.o_scales, req->tile_scales,
+             p.dtype == TNO_F32 ? 0 : (size_t)p.T * ((p.H + 63) / 64) * ((p.W + 63) / 64) * 4},
+            {p.o_sigma, req->sigma, HW * 4},
+            {p.o_times, req->times, (size_t)p.T * 8},
+            {p.o_vel, req->velocities, (size_t)p.J * 16},
+        };
+        for (auto &c : cps)
+            if (c.bytes && (e = hipMemcpy(at<void>(A, c.off), c.src, c.bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+                release(h, q);
+                return hip_fail(e, "copying inputs", nullptr, 0);
+            }
+    }
+    if ((e = enqueue(h, q, req)) != hipSuccess) {
+        (void)hipStreamSynchronize(h->stream);
+        release(h, q);
+        return hip_fail(e, "enqueue", nullptr, 0);
+    }
+    q->ticket = h->next_ticket++;
+    h->live[q->ticket] = q;
+    *out_ticket = q->ticket;
+    return TNO_OK;
+}
+
+int tno_search_poll(tno_search *h, uint64_t ticket, int32_t timeout_ms, tno_result *out_result)
+{
+    if (!h || !out_result) {
+        set_last(fail(TNO_E_INVAL, "handle or out_result is NULL"));
+        return TNO_E_INVAL;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lock(h->mu);
+            auto it = h->live.find(ticket);
+            if (it == h->live.end()) {
+                set_last(fail(TNO_E_TICKET, "unknown or collected ticket %llu", (unsigned long long)ticket));
+                return TNO_E_TICKET;
+            }
+            Request *q = it->second;
+            (void)hipSetDevice(h->device);
+            hipError_t e = hipEventQuery(q->ev[5]);
+            if (e == hipSuccess) {
+                tno_result res;
+                memset(&res, 0, sizeof res);
+                res.status = TNO_OK;
+                res.updates = q->updates;
+                res.n_topk = q->plan.k;
+                float ms = 0.0f;
+                if (hipEventElapsedTime(&ms, q->ev[0], q->ev[5]) == hipSuccess)
+                    res.device_ms = ms;
+                double *ph[5] = {&res.prep_ms, &res.table_ms, &res.lambda_ms, &res.search_ms, &res.reduce_ms};
+                for (int i = 0; i < 5; ++i)
+                    if (hipEventElapsedTime(&ms, q->ev[i], q->ev[i + 1]) == hipSuccess)
+                        *ph[i] = ms;
+                int32_t err = 0;
+                hipError_t e2 = hipMemcpy(&err, at<void>(q->arena, q->plan.o_err), 4, hipMemcpyDeviceToHost);
+                if (e2 == hipSuccess)
+                    e2 = finish_outputs(q);
+                if (e2 != hipSuccess) {
+                    res.status = TNO_E_DEVICE;
+                    snprintf(res.message, sizeof res.message, "%s", hipGetErrorString(e2));
+                } else if (err) {
+                    res.status = TNO_E_INTERNAL;
+                    snprintf(res.message, sizeof res.message, "trail run exceeded its planned capacity");
+                }
+                auto t1 = std::chrono::steady_clock::now();
+                res.total_ms = std::chrono::duration<double, std::milli>(t1 - q->t_submit).count();
+                res.queue_ms = std::max(0.0, res.total_ms - res.device_ms);
+                h->live.erase(it);
+                release(h, q);
+                *out_result = res;
+                return res.status;
+            }
+            if (e != hipErrorNotReady) {
+                tno_result res;
+                memset(&res, 0, sizeof res);
+                res.status = TNO_E_DEVICE;
+                snprintf(res.message, sizeof res.message, "%s", hipGetErrorString(e));
+                (void)hipStreamSynchronize(h->stream);
+                h->live.erase(it);
+                release(h, q);
+                *out_result = res;
+                return TNO_E_DEVICE;
+            }
+        }
+        if (timeout_ms == 0)
+            return TNO_PENDING;
+        auto el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (timeout_ms > 0 && el >= timeout_ms)
+            return TNO_PENDING;
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+}
+
+int tno_quantize(int32_t n_frames, int32_t height, int32_t width, int32_t dtype,
+                 const float *residuals, void *codes, float *tile_scales, void *stream)
+{
+    if (n_frames <= 0 || height <= 0 || width <= 0 || n_frames > 65535 || height > 32768 ||
+        width > 32768 || !residuals || !codes || !tile_scales ||
+        (dtype != TNO_BF16 && dtype != TNO_F16 && dtype != TNO_FP8_E4M3)) {
+        set_last(fail(TNO_E_INVAL, "tno_quantize: bad arguments"));
+        return TNO_E_INVAL;
+    }
+    hipError_t e = tno::launch_quantize((hipStream_t)stream, dtype, residuals, n_frames, height, width,
+                                        codes, tile_scales);
+    if (e != hipSuccess)
+        return hip_fail(e, "tno_quantize", nullptr, 0);
+    return TNO_OK;
+}
+
+void tno_search_destroy(tno_search *h)
+{
+    if (!h)
+        return;
+    {
+        std::lock_guard<std::mutex> lock(h->mu);
+        (void)hipSetDevice(h->device);
+        (void)hipStreamSynchronize(h->stream);
+        for (auto &kv : h->live)
+            release(h, kv.second);
+        h->live.clear();
+        h->cache.trim(0);
+        if (h->own_stream)
+            (void)hipStreamDestroy(h->stream);
+    }
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,309 @@
+"""Thin ctypes binding of libtno_search.so (include/tno_search.h).
+
+Argument marshalling only: every step of the search runs in the library's HIP
+kernels.  The functions keep the C names; `search_tensors` is a convenience
+that fills the structs from torch tensors already on the GPU and runs one
+request on torch's current stream.  Importing this module without the built
+library raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtno_search.so")
+
+TNO_OK = 0
+TNO_PENDING = 1
+TNO_E_INVAL = -1
+TNO_E_NOMEM = -2
+TNO_E_BUSY = -3
+TNO_E_DEVICE = -4
+TNO_E_TICKET = -5
+TNO_E_CANCELLED = -6
+TNO_E_INTERNAL = -7
+
+TNO_F32, TNO_BF16, TNO_F16, TNO_FP8_E4M3 = 0, 1, 2, 3
+TNO_PRF_GAUSS_SAMPLED, TNO_PRF_GAUSS_INTEGRATED = 0, 1
+TNO_CFG_GRAPHS = 1
+TNO_REQ_DEVICE_PTRS = 1
+TNO_REQ_VALIDATE = 2
+TNO_MAX_TOPK = 1024
+TNO_MAX_STAMP = 15
+TNO_QTILE = 64
+
+DTYPE_CODE = {"f32": TNO_F32, "bf16": TNO_BF16, "f16": TNO_F16, "fp8_e4m3": TNO_FP8_E4M3}
+
+_vp = ctypes.c_void_p
+
+
+class tno_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("stream", _vp), ("tune_cache_path", ctypes.c_char_p)]
+
+
+class tno_prf(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("stamp", ctypes.c_int32), ("sigma_px", ctypes.c_double)]
+
+
+class tno_request(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("n_frames", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("residuals", _vp), ("tile_scales", _vp), ("sigma", _vp), ("times", _vp),
+                ("t_ref", ctypes.c_double), ("prf", tno_prf), ("n_traj", ctypes.c_int32),
+                ("top_k", ctypes.c_int32), ("velocities", _vp), ("stack_key", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class tno_peak(ctypes.Structure):
+    _fields_ = [("snr", ctypes.c_float), ("flux", ctypes.c_float), ("y", ctypes.c_int32),
+                ("x", ctypes.c_int32)]
+
+
+class tno_candidate(ctypes.Structure):
+    _fields_ = [("snr", ctypes.c_float), ("flux", ctypes.c_float), ("traj", ctypes.c_int32),
+                ("y", ctypes.c_int32), ("x", ctypes.c_int32)]
+
+
+class tno_outputs(ctypes.Structure):
+    _fields_ = [("snr", _vp), ("flux", _vp), ("best_snr", _vp), ("best_traj", _vp),
+                ("traj_max", _vp), ("topk", _vp)]
+
+
+class tno_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_topk", ctypes.c_int32),
+                ("updates", ctypes.c_uint64), ("queue_ms", ctypes.c_double),
+                ("device_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("prep_ms", ctypes.c_double), ("table_ms", ctypes.c_double),
+                ("lambda_ms", ctypes.c_double), ("search_ms", ctypes.c_double),
+                ("reduce_ms", ctypes.c_double), ("message", ctypes.c_char * 160)]
+
+
+EXPORTS = ("tno_search_create", "tno_search_submit", "tno_search_poll", "tno_search_destroy",
+           "tno_search_validate", "tno_search_footprint", "tno_search_last_error", "tno_quantize")
+
+
+class TnoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("tno status %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libtno_search.so not built (run __graft_entry__.build() or "
+                           "python -m paper_2209_09848_amd.build): %s" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.tno_search_create.argtypes = [P(tno_config), P(_vp)]
+    lib.tno_search_create.restype = ctypes.c_int
+    lib.tno_search_submit.argtypes = [_vp, P(tno_request), P(tno_outputs), P(ctypes.c_uint64)]
+    lib.tno_search_submit.restype = ctypes.c_int
+    lib.tno_search_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.c_int32, P(tno_result)]
+    lib.tno_search_poll.restype = ctypes.c_int
+    lib.tno_search_destroy.argtypes = [_vp]
+    lib.tno_search_destroy.restype = None
+    lib.tno_search_validate.argtypes = [P(tno_request), P(tno_outputs), ctypes.c_char_p, ctypes.c_int32]
+    lib.tno_search_validate.restype = ctypes.c_int
+    lib.tno_search_footprint.argtypes = [P(tno_request), P(tno_outputs)]
+    lib.tno_search_footprint.restype = ctypes.c_uint64
+    lib.tno_search_last_error.argtypes = []
+    lib.tno_search_last_error.restype = ctypes.c_char_p
+    lib.tno_quantize.argtypes = [ctypes.c_int32] * 4 + [_vp, _vp, _vp, _vp]
+    lib.tno_quantize.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+# ------------------------------------------------------------------ C-named calls
+
+def tno_search_last_error() -> str:
+    return load().tno_search_last_error().decode(errors="replace")
+
+
+def tno_search_create(cfg: tno_config):
+    h = _vp()
+    rc = load().tno_search_create(ctypes.byref(cfg), ctypes.byref(h))
+    if rc != TNO_OK:
+        raise TnoError(rc, tno_search_last_error())
+    return h
+
+
+def tno_search_submit(h, req: tno_request, out: tno_outputs):
+    """Returns (status, ticket); ticket is None unless status == TNO_OK."""
+    t = ctypes.c_uint64()
+    rc = load().tno_search_submit(h, ctypes.byref(req), ctypes.byref(out), ctypes.byref(t))
+    return rc, (t.value if rc == TNO_OK else None)
+
+
+def tno_search_poll(h, ticket: int, timeout_ms: int = -1):
+    """Returns (status, tno_result or None if pending)."""
+    res = tno_result()
+    rc = load().tno_search_poll(h, ctypes.c_uint64(ticket), int(timeout_ms), ctypes.byref(res))
+    return rc, (None if rc == TNO_PENDING else res)
+
+
+def tno_search_destroy(h) -> None:
+    load().tno_search_destroy(h)
+
+
+def tno_search_validate(req: tno_request, out: tno_outputs):
+    buf = ctypes.create_string_buffer(256)
+    rc = load().tno_search_validate(ctypes.byref(req), ctypes.byref(out), buf, 256)
+    return rc, buf.value.decode(errors="replace")
+
+
+def tno_search_footprint(req: tno_request, out: tno_outputs) -> int:
+    return int(load().tno_search_footprint(ctypes.byref(req), ctypes.byref(out)))
+
+
+def tno_quantize(T, H, W, dtype, residuals_ptr, codes_ptr, scales_ptr, stream=None) -> int:
+    return int(load().tno_quantize(int(T), int(H), int(W), int(dtype), residuals_ptr, codes_ptr,
+                                   scales_ptr, stream))
+
+
+# ------------------------------------------------------------------ torch convenience
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def make_request(R, sigma, times, vel, *, t_ref=float("nan"), dtype="f32", scales=None,
+                 sigma_px=0.7, stamp=5, prf_kind=TNO_PRF_GAUSS_SAMPLED, top_k=10,
+                 stack_key=0, flags=TNO_REQ_DEVICE_PTRS) -> tno_request:
+    """A request over torch tensors on the GPU (device pointers)."""
+    T, H, W = (int(s) for s in R.shape)
+    req = tno_request()
+    req.height, req.width, req.n_frames = H, W, T
+    req.dtype = DTYPE_CODE[dtype] if isinstance(dtype, str) else int(dtype)
+    req.residuals = _ptr(R)
+    req.tile_scales = _ptr(scales)
+    req.sigma = _ptr(sigma)
+    req.times = _ptr(times)
+    req.t_ref = float(t_ref) if t_ref is not None else float("nan")
+    req.prf = tno_prf(int(prf_kind), int(stamp), float(sigma_px))
+    req.n_traj = int(vel.shape[0])
+    req.top_k = int(top_k)
+    req.velocities = _ptr(vel)
+    req.stack_key = int(stack_key)
+    req.flags = int(flags)
+    req.reserved = 0
+    return req
+
+
+class Search:
+    """One handle on torch's current stream of `device` (default cuda:0)."""
+
+    def __init__(self, device: int = 0, max_inflight: int = 64, hbm_budget_bytes: int = 0,
+                 stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        cfg = tno_config()
+        cfg.device = device
+        cfg.max_inflight = max_inflight
+        cfg.hbm_budget_bytes = hbm_budget_bytes
+        cfg.flags = 0
+        cfg.reserved = 0
+        cfg.stream = ctypes.c_void_p(stream)
+        cfg.tune_cache_path = None
+        self.device = device
+        self.h = tno_search_create(cfg)
+
+    def close(self):
+        if self.h is not None:
+            tno_search_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, req: tno_request, out: tno_outputs) -> int:
+        rc, t = tno_search_submit(self.h, req, out)
+        if rc != TNO_OK:
+            raise TnoError(rc, tno_search_last_error())
+        return t
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> tno_result:
+        rc, res = tno_search_poll(self.h, ticket, timeout_ms)
+        if rc == TNO_PENDING:
+            raise TimeoutError("ticket %d still pending" % ticket)
+        if rc != TNO_OK:
+            msg = res.message.decode(errors="replace") if res is not None else tno_search_last_error()
+            raise TnoError(rc, msg)
+        return res
+
+
+def alloc_outputs(J, H, W, k, device="cuda", maps=True):
+    """Torch output buffers and the tno_outputs struct that points at them."""
+    import torch
+    o = {}
+    if maps:
+        o["snr"] = torch.empty((J, H, W), dtype=torch.float32, device=device)
+        o["flux"] = torch.empty((J, H, W), dtype=torch.float32, device=device)
+    o["best_snr"] = torch.empty((H, W), dtype=torch.float32, device=device)
+    o["best_traj"] = torch.empty((H, W), dtype=torch.int32, device=device)
+    o["traj_max"] = torch.empty((J, 4), dtype=torch.int32, device=device)   # tno_peak
+    o["topk"] = torch.empty((max(k, 1), 5), dtype=torch.int32, device=device)  # tno_candidate
+    out = tno_outputs()
+    out.snr = _ptr(o.get("snr"))
+    out.flux = _ptr(o.get("flux"))
+    out.best_snr = _ptr(o["best_snr"])
+    out.best_traj = _ptr(o["best_traj"])
+    out.traj_max = _ptr(o["traj_max"])
+    out.topk = _ptr(o["topk"]) if k > 0 else None
+    return o, out
+
+
+def decode_peaks(t):
+    """[J][4] int32 tensor of tno_peak -> (snr, flux, y, x) numpy arrays."""
+    import numpy as np
+    a = t.cpu().numpy()
+    return (a[:, 0].view(np.float32).copy(), a[:, 1].view(np.float32).copy(),
+            a[:, 2].copy(), a[:, 3].copy())
+
+
+def decode_candidates(t, n):
+    """[k][5] int32 tensor of tno_candidate -> list of (snr, flux, traj, y, x)."""
+    import numpy as np
+    a = t.cpu().numpy()[:n]
+    s = a[:, 0].view(np.float32)
+    f = a[:, 1].view(np.float32)
+    return [(float(s[i]), float(f[i]), int(a[i, 2]), int(a[i, 3]), int(a[i, 4])) for i in range(n)]
+
+
+def search_tensors(R, sigma, times, vel, *, top_k=10, maps=True, handle: Search | None = None,
+                   **kw):
+    """Run one search over GPU tensors; returns (outputs dict, tno_result)."""
+    T, H, W = (int(s) for s in R.shape)
+    J = int(vel.shape[0])
+    o, out = alloc_outputs(J, H, W, top_k, device=R.device, maps=maps)
+    req = make_request(R, sigma, times, vel, top_k=top_k, **kw)
+    own = handle is None
+    h = Search(R.device.index or 0) if own else handle
+    try:
+        t = h.submit(req, out)
+        res = h.wait(t)
+    finally:
+        if own:
+            h.close()
+    return o, res

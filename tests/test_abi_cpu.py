@@ -1,0 +1,126 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/tno_search.h declares, and its validation and
+footprint helpers behave."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2209_09848_amd import tno
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tno_search.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|uint64_t|const char \*)\s*\**\s*(tno_\w+)\s*\(",
+                                 txt, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for name in ("tno_search_create", "tno_search_submit", "tno_search_poll", "tno_search_destroy"):
+        assert name in fns
+    assert set(fns) == set(tno.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = tno.load()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def _host_request(H=16, W=20, T=5, J=3, **kw):
+    R = np.zeros((T, H, W), np.float32)
+    sigma = np.ones((H, W), np.float32)
+    times = 2000.0 + np.arange(T) / 48.0
+    vel = np.array([[1.0, 2.0]] * J)
+    keep = [R, sigma, times, vel]
+    req = tno.tno_request()
+    req.height, req.width, req.n_frames, req.dtype = H, W, T, tno.TNO_F32
+    req.residuals = R.ctypes.data_as(ctypes.c_void_p)
+    req.tile_scales = None
+    req.sigma = sigma.ctypes.data_as(ctypes.c_void_p)
+    req.times = times.ctypes.data_as(ctypes.c_void_p)
+    req.t_ref = math.nan
+    req.prf = tno.tno_prf(0, 5, 0.7)
+    req.n_traj = J
+    req.top_k = 0
+    req.velocities = vel.ctypes.data_as(ctypes.c_void_p)
+    req.stack_key = 0
+    req.flags = 0
+    req.reserved = 0
+    for k, v in kw.items():
+        setattr(req, k, v)
+    return req, tno.tno_outputs(), keep
+
+
+def test_validate_accepts_a_good_request():
+    req, out, keep = _host_request()
+    rc, msg = tno.tno_search_validate(req, out)
+    assert rc == tno.TNO_OK, msg
+    assert tno.tno_search_footprint(req, out) > 0
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("height", 0, "positive"), ("n_frames", -1, "positive"), ("n_traj", 0, "n_traj"),
+    ("dtype", 9, "dtype"), ("reserved", 1, "reserved"), ("top_k", 2000, "top_k"),
+    ("top_k", 5, "topk"), ("flags", 0x80, "flags"), ("t_ref", math.inf, "t_ref"),
+])
+def test_validate_rejects(field, value, needle):
+    req, out, keep = _host_request()
+    setattr(req, field, value)
+    rc, msg = tno.tno_search_validate(req, out)
+    assert rc == tno.TNO_E_INVAL and needle in msg, msg
+
+
+@pytest.mark.parametrize("stamp,sp", [(4, 0.7), (0, 0.7), (17, 0.7), (5, 0.0), (5, math.nan)])
+def test_validate_rejects_prf(stamp, sp):
+    req, out, keep = _host_request()
+    req.prf = tno.tno_prf(0, stamp, sp)
+    rc, msg = tno.tno_search_validate(req, out)
+    assert rc == tno.TNO_E_INVAL
+
+
+def test_validate_rejects_nonfinite_times_and_velocities():
+    req, out, keep = _host_request()
+    keep[2][3] = np.nan
+    assert tno.tno_search_validate(req, out)[0] == tno.TNO_E_INVAL
+    req, out, keep = _host_request()
+    keep[3][1, 0] = np.inf
+    assert tno.tno_search_validate(req, out)[0] == tno.TNO_E_INVAL
+    req, out, keep = _host_request()
+    keep[3][0, 1] = 1e12     # moves more than 1e9 px over the baseline
+    assert tno.tno_search_validate(req, out)[0] == tno.TNO_E_INVAL
+
+
+def test_validate_needs_scales_for_reduced_precision():
+    req, out, keep = _host_request()
+    req.dtype = tno.TNO_BF16
+    rc, msg = tno.tno_search_validate(req, out)
+    assert rc == tno.TNO_E_INVAL and "tile_scales" in msg
+
+
+def test_footprint_grows_with_bank_and_shift():
+    req, out, keep = _host_request(J=2)
+    f2 = tno.tno_search_footprint(req, out)
+    req8, out8, keep8 = _host_request(J=8)
+    assert tno.tno_search_footprint(req8, out8) > f2
+    req, out, keep = _host_request(J=2)
+    keep[3][:] = [[400.0, -300.0]]  # ~8 px/frame: padding and trail boxes grow
+    assert tno.tno_search_footprint(req, out) > f2
+
+
+def test_create_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    cfg = tno.tno_config()
+    cfg.device = 0
+    with pytest.raises(tno.TnoError) as e:
+        tno.tno_search_create(cfg)
+    assert e.value.code == tno.TNO_E_DEVICE

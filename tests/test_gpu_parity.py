@@ -1,0 +1,305 @@
+"""GPU parity: the HIP search through the C ABI against the FP64 oracle.
+
+Full maps on small problems that still span several tiles and ragged edges;
+sampled hypotheses and reduction properties at the full FFI size.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import codec, oracle
+from paper_2209_09848_amd import synth, tno
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _to(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def run_gpu(R, sigma, times, vel, t_ref, top_k=10, stamp=5, sigma_px=0.7, prf_kind=0,
+            dtype="f32", scales=None, handle=None):
+    Rt = R if isinstance(R, torch.Tensor) else _to(R)
+    o, res = tno.search_tensors(Rt, _to(sigma), _to(times), _to(vel), t_ref=t_ref, top_k=top_k,
+                                stamp=stamp, sigma_px=sigma_px, prf_kind=prf_kind, dtype=dtype,
+                                scales=None if scales is None else (scales if isinstance(scales, torch.Tensor) else _to(scales)),
+                                handle=handle)
+    torch.cuda.synchronize()
+    J = vel.shape[0]
+    out = {
+        "snr": o["snr"].cpu().numpy(), "flux": o["flux"].cpu().numpy(),
+        "best_snr": o["best_snr"].cpu().numpy(), "best_traj": o["best_traj"].cpu().numpy(),
+        "traj_max": tno.decode_peaks(o["traj_max"]),
+        "topk": tno.decode_candidates(o["topk"], res.n_topk) if top_k > 0 else [],
+    }
+    assert res.status == 0 and res.updates == J * R.shape[0] * R.shape[1] * R.shape[2]
+    return out, res
+
+
+def full_check(R, sigma, times, vel, t_ref, top_k=10, **kw):
+    print("case: T,H,W=%s J=%d k=%d %s" % (tuple(R.shape), vel.shape[0], top_k, kw), flush=True)
+    g, res = run_gpu(R, sigma, times, vel, t_ref, top_k=top_k, **kw)
+    okw = {k: v for k, v in kw.items() if k in ("stamp", "sigma_px", "prf_kind")}
+    o = oracle.search(R, sigma, times, t_ref, vel, **okw)
+    es, ef = parity.check_maps(g["snr"], g["flux"], o)
+    parity.check_best(g["best_snr"], g["best_traj"], o["snr"])
+    parity.check_traj_max(g["traj_max"], o["snr"], o["flux"])
+    if top_k > 0:
+        parity.check_topk(g["topk"], o["snr"], top_k)
+    return g, o, (es, ef)
+
+
+@pytest.mark.parametrize("variant", ["noisy", "noise_free", "bright"])
+def test_c1_full_parity(variant):
+    p = synth.make_c1(variant)
+    g, o, err = full_check(p.R, p.sigma, p.times, p.vel, p.t_ref, top_k=p.top_k)
+    if variant != "noisy":
+        j, y, x = np.unravel_index(np.argmax(g["snr"]), g["snr"].shape)
+        assert (j, y, x) == (4, 32, 20)
+    if variant == "noise_free":
+        assert abs(g["snr"][4, 32, 20] - 1.2986868495) < 2e-5
+
+
+def _rand_problem(seed, T, H, W, J, vmax=20.0, mask=True, gap=True):
+    g = np.random.default_rng(seed)
+    R = g.standard_normal((T, H, W)).astype(np.float32)
+    sigma = synth.sigma_lognormal(g, H, W)
+    if mask and H * W > 8:
+        for _ in range(max(1, H * W // 50)):
+            sigma[g.integers(0, H), g.integers(0, W)] = g.choice([0.0, -1.0, np.nan, np.inf])
+    times = synth.times_with_gap(T, T // 2, 0.9) if gap and T > 2 else synth.times_uniform(T)
+    vel = g.uniform(-vmax, vmax, size=(J, 2))
+    return R, sigma, times, vel
+
+
+@pytest.mark.parametrize("T,H,W,J,stamp,kind", [
+    (9, 37, 133, 4, 5, 0),       # ragged in both axes, several tiles
+    (12, 70, 260, 3, 5, 1),      # integrated PRF
+    (6, 33, 129, 2, 1, 0),       # single-tap stamp
+    (6, 40, 70, 2, 3, 0),
+    (5, 45, 50, 2, 7, 1),
+    (4, 50, 140, 2, 15, 0),      # widest stamp
+    (300, 34, 40, 3, 5, 0),      # many frame chunks
+    (1, 1, 1, 1, 5, 0),          # a single pixel, a single frame
+    (3, 2, 3, 2, 3, 0),          # fewer elements than top_k
+])
+def test_edge_shapes(T, H, W, J, stamp, kind):
+    R, sigma, times, vel = _rand_problem(1000 + T + H, T, H, W, J)
+    full_check(R, sigma, times, vel, float(times[0]), top_k=25, stamp=stamp, prf_kind=kind,
+               sigma_px=0.9 if kind else 0.7)
+
+
+def test_explicit_reference_time_and_negative_baselines():
+    R, sigma, times, vel = _rand_problem(7, 10, 40, 150, 3)
+    full_check(R, sigma, times, vel, float(times[6]) + 0.013, top_k=10)
+
+
+def test_trails_leaving_the_image_and_the_padding():
+    # 6000 px/day over 5 cadences moves ~625 px: beyond the image and the
+    # staged stack's zero border; many start pixels have Lam = 0
+    R, sigma, times, vel = _rand_problem(8, 6, 40, 130, 3)
+    vel = np.array([[6000.0, 10.0], [-300.0, 2500.0], [3.0, -4.0]])
+    full_check(R, sigma, times, vel, float(times[0]), top_k=10)
+
+
+def test_all_zero_residuals_ties_go_to_smallest_index():
+    R = np.zeros((4, 20, 30), np.float32)
+    sigma = np.ones((20, 30), np.float32)
+    times = synth.times_uniform(4)
+    vel = np.array([[1.0, 0.0], [0.0, -1.0]])
+    g, res = run_gpu(R, sigma, times, vel, float(times[0]), top_k=17)
+    assert np.all(g["snr"] == 0)
+    assert [(c[2], c[3], c[4]) for c in g["topk"]] == [(0, i // 30, i % 30) for i in range(17)]
+    assert np.all(g["best_traj"] == 0)
+    s, f, y, x = g["traj_max"]
+    assert list(y) == [0, 0] and list(x) == [0, 0]
+
+
+def test_deterministic_repeat():
+    R, sigma, times, vel = _rand_problem(9, 20, 64, 200, 4)
+    a, _ = run_gpu(R, sigma, times, vel, float(times[0]), top_k=50)
+    b, _ = run_gpu(R, sigma, times, vel, float(times[0]), top_k=50)
+    for k in ("snr", "flux", "best_snr", "best_traj"):
+        assert np.array_equal(a[k], b[k])
+    assert a["topk"] == b["topk"]
+
+
+def test_host_pointer_path_matches_device_path():
+    R, sigma, times, vel = _rand_problem(10, 8, 36, 140, 3)
+    dev, _ = run_gpu(R, sigma, times, vel, float(times[0]), top_k=12)
+    J, (T, H, W) = vel.shape[0], R.shape
+    snr = np.zeros((J, H, W), np.float32)
+    flux = np.zeros((J, H, W), np.float32)
+    best = np.zeros((H, W), np.float32)
+    bestj = np.zeros((H, W), np.int32)
+    peaks = (tno.tno_peak * J)()
+    cands = (tno.tno_candidate * 12)()
+    import ctypes
+    req = tno.tno_request()
+    req.height, req.width, req.n_frames, req.dtype = H, W, T, tno.TNO_F32
+    req.residuals = R.ctypes.data_as(ctypes.c_void_p)
+    req.sigma = sigma.ctypes.data_as(ctypes.c_void_p)
+    req.times = times.ctypes.data_as(ctypes.c_void_p)
+    req.t_ref = float(times[0])
+    req.prf = tno.tno_prf(0, 5, 0.7)
+    req.n_traj = J
+    req.top_k = 12
+    req.velocities = vel.ctypes.data_as(ctypes.c_void_p)
+    out = tno.tno_outputs()
+    out.snr = snr.ctypes.data_as(ctypes.c_void_p)
+    out.flux = flux.ctypes.data_as(ctypes.c_void_p)
+    out.best_snr = best.ctypes.data_as(ctypes.c_void_p)
+    out.best_traj = bestj.ctypes.data_as(ctypes.c_void_p)
+    out.traj_max = ctypes.cast(peaks, ctypes.c_void_p)
+    out.topk = ctypes.cast(cands, ctypes.c_void_p)
+    with tno.Search(0) as h:
+        t = h.submit(req, out)
+        res = h.wait(t)
+    assert res.status == 0 and res.n_topk == 12
+    assert np.array_equal(snr, dev["snr"]) and np.array_equal(flux, dev["flux"])
+    assert np.array_equal(best, dev["best_snr"]) and np.array_equal(bestj, dev["best_traj"])
+    assert [(c.snr, c.traj, c.y, c.x) for c in cands] == [(c[0], c[2], c[3], c[4]) for c in dev["topk"]]
+
+
+# ------------------------------------------------------------------ precision form
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16", "fp8_e4m3"])
+def test_quantize_matches_oracle_codec_bit_exactly(dtype):
+    g = np.random.default_rng(21)
+    T, H, W = 5, 100, 150
+    R = (g.standard_normal((T, H, W)) * np.exp(2 * g.standard_normal((T, H, W)))).astype(np.float32)
+    R[2, 64:, :64] = 0.0
+    R[3, 10, 10] = 2.0 ** -140  # FP32 subnormal input
+    codes_o, scales_o = codec.quantize(R, dtype)
+    Rt = _to(R)
+    ct = torch.empty((T, H, W), dtype=torch.uint8 if dtype == "fp8_e4m3" else torch.int16, device=DEV)
+    st = torch.empty((T, (H + 63) // 64, (W + 63) // 64), dtype=torch.float32, device=DEV)
+    rc = tno.tno_quantize(T, H, W, tno.DTYPE_CODE[dtype], Rt.data_ptr(), ct.data_ptr(), st.data_ptr(),
+                          None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    codes = ct.cpu().numpy().view(np.uint8 if dtype == "fp8_e4m3" else np.uint16)
+    assert np.array_equal(st.cpu().numpy(), scales_o)
+    assert np.array_equal(codes, codes_o)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16", "fp8_e4m3"])
+def test_precision_search_parity_on_dequantized_values(dtype):
+    R, sigma, times, vel = _rand_problem(30, 12, 70, 140, 3)
+    codes, scales = codec.quantize(R, dtype)
+    deq = codec.dequantize(codes, scales, dtype)
+    ct = _to(codes.view(np.int16) if dtype != "fp8_e4m3" else codes)
+    print("precision case", dtype, flush=True)
+    o_, r_ = tno.search_tensors(ct, _to(sigma), _to(times), _to(vel), t_ref=float(times[0]),
+                                top_k=10, dtype=dtype, scales=_to(scales))
+    torch.cuda.synchronize()
+    o = oracle.search(deq, sigma, times, float(times[0]), vel)
+    parity.check_maps(o_["snr"].cpu().numpy(), o_["flux"].cpu().numpy(), o)
+    parity.check_topk(tno.decode_candidates(o_["topk"], r_.n_topk), o["snr"], 10)
+
+
+# ------------------------------------------------------------------ API behaviour on the GPU
+
+def _small_request(k=5):
+    R, sigma, times, vel = _rand_problem(40, 6, 30, 40, 2)
+    t = [_to(R), _to(sigma), _to(times), _to(vel)]
+    req = tno.make_request(*t, t_ref=float(times[0]), top_k=k)
+    o, out = tno.alloc_outputs(2, 30, 40, k)
+    return req, out, (t, o)
+
+
+def test_tickets_budget_and_backpressure():
+    req, out, keep = _small_request()
+    with tno.Search(0, max_inflight=1) as h:
+        t1 = h.submit(req, out)
+        rc, t2 = tno.tno_search_submit(h.h, req, out)
+        assert rc == tno.TNO_E_BUSY and t2 is None
+        res = h.wait(t1)
+        assert res.status == 0
+        rc, _ = tno.tno_search_poll(h.h, t1, 0)
+        assert rc == tno.TNO_E_TICKET
+        rc, _ = tno.tno_search_poll(h.h, 987654, 0)
+        assert rc == tno.TNO_E_TICKET
+    with tno.Search(0, hbm_budget_bytes=4096) as h:
+        rc, t = tno.tno_search_submit(h.h, req, out)
+        assert rc == tno.TNO_E_NOMEM
+    bad = tno.make_request(*keep[0], top_k=5)
+    bad.prf = tno.tno_prf(0, 4, 0.7)
+    with tno.Search(0) as h:
+        rc, t = tno.tno_search_submit(h.h, bad, out)
+        assert rc == tno.TNO_E_INVAL
+        # destroy with work still pending frees everything
+        h.submit(req, out)
+
+
+# ------------------------------------------------------------------ full FFI size, sampled
+
+def _crop_oracle(R_dev, sigma, times, t_ref, vel, y0, y1, x0, x1, margin):
+    T, H, W = R_dev.shape
+    cy0, cy1 = max(0, y0 - margin), min(H, y1 + margin)
+    cx0, cx1 = max(0, x0 - margin), min(W, x1 + margin)
+    Rc = R_dev[:, cy0:cy1, cx0:cx1].cpu().numpy()
+    o = oracle.search(Rc, sigma[cy0:cy1, cx0:cx1], times, t_ref, vel,
+                      region=(y0 - cy0, y1 - cy0, x0 - cx0, x1 - cx0))
+    return o
+
+
+@pytest.mark.slow
+def test_ffi_full_size_sampled_parity():
+    """2048x2048 px x 1000 frames, 100 trajectories, 30 sources: the launch
+    configuration the benchmark times.  Oracle on sampled start pixels (all
+    trajectories) in a corner, an edge and the centre, and at injected
+    sources; reductions checked against torch ops on the GPU's own maps."""
+    H = W = 2048
+    T = 1000
+    print("generating FFI-size problem", flush=True)
+    R, sigma, times, t_ref, vel, src = synth.make_ffi_like_torch(H, W, T, DEV)
+    J = vel.shape[0]
+    k = 100
+    o, res = tno.search_tensors(R, _to(sigma), _to(times), _to(vel), t_ref=t_ref, top_k=k)
+    torch.cuda.synchronize()
+    print("search done: device %.1f ms, %.3g updates/s" % (res.device_ms, res.updates / (res.device_ms * 1e-3)), flush=True)
+    snr, flux = o["snr"], o["flux"]
+    # reductions vs torch on the same FP32 maps
+    best = snr.max(dim=0).values
+    assert torch.equal(o["best_snr"], best)
+    first = (snr == best[None]).to(torch.uint8).argmax(dim=0).to(torch.int32)
+    assert torch.equal(o["best_traj"], first)
+    del first
+    fl = snr.reshape(J, -1)
+    mx = fl.max(dim=1).values
+    am = (fl == mx[:, None]).to(torch.uint8).argmax(dim=1).cpu().numpy()
+    ps, pf, py, px = tno.decode_peaks(o["traj_max"])
+    assert np.array_equal(ps, mx.cpu().numpy())
+    assert np.array_equal(py * W + px, am)
+    flat = snr.reshape(-1)
+    tv = torch.topk(flat, k).values.cpu().numpy()
+    cands = tno.decode_candidates(o["topk"], res.n_topk)
+    assert np.array_equal(np.array([c[0] for c in cands], np.float32), tv)
+    kth = tv[-1]
+    gt = torch.nonzero(flat > float(kth)).reshape(-1).cpu().numpy()
+    eq = torch.nonzero(flat == float(kth)).reshape(-1).cpu().numpy()
+    want = set(gt.tolist()) | set(eq[:k - gt.size].tolist())
+    got = {c[2] * H * W + c[3] * W + c[4] for c in cands}
+    assert got == want
+    # oracle on sampled start pixels, all trajectories
+    margin = int(math.ceil(np.abs(vel).max() * (times.max() - t_ref))) + 4
+    for (y0, x0) in [(0, 0), (1020, 1020), (2040, 1500), (700, 2042)]:
+        y1, x1 = min(H, y0 + 8), min(W, x0 + 8)
+        print("oracle region", y0, x0, flush=True)
+        ora = _crop_oracle(R, sigma, times, t_ref, vel, y0, y1, x0, x1, margin)
+        sub = {"snr": snr[:, y0:y1, x0:x1].cpu().numpy(), "flux": flux[:, y0:y1, x0:x1].cpu().numpy()}
+        parity.check_maps(sub["snr"], sub["flux"], ora)
+    # injected sources: truth trajectory around the rounded start
+    for s in src[:6]:
+        j = s.traj
+        yr, xr = int(math.floor(s.y + 0.5)), int(math.floor(s.x + 0.5))
+        y0, y1, x0, x1 = max(0, yr - 1), min(H, yr + 2), max(0, xr - 1), min(W, xr + 2)
+        ora = _crop_oracle(R, sigma, times, t_ref, vel[j:j + 1], y0, y1, x0, x1, margin)
+        parity.check_maps(snr[j:j + 1, y0:y1, x0:x1].cpu().numpy(),
+                          flux[j:j + 1, y0:y1, x0:x1].cpu().numpy(), ora)
