@@ -6,10 +6,13 @@
 
 namespace tno {
 
-// Search tile: 128 start-pixel columns (2 per lane) x 32 rows (8 per lane, 4 waves).
+// Search tile: 128 start-pixel columns (2 per lane) x SEARCH_TY rows (8 per
+// lane, one wave per 8 rows).
 constexpr int SEARCH_TX = 128;
-constexpr int SEARCH_TY = 32;
-constexpr int SEARCH_THREADS = 256;
+constexpr int SEARCH_RPL = 8;
+constexpr int SEARCH_WAVES = 4;
+constexpr int SEARCH_TY = SEARCH_RPL * SEARCH_WAVES;
+constexpr int SEARCH_THREADS = 64 * SEARCH_WAVES;
 // Normaliser tile: 64 columns (1 per lane) x 32 rows (8 per lane, 4 waves).
 constexpr int LAMBDA_TX = 64;
 constexpr int LAMBDA_TY = 32;
@@ -25,7 +28,7 @@ struct TrailInfo {
     int32_t ncols;     // columns in the box (clipped to |qx| < W)
     int32_t qy_lo;     // smallest row offset kept (clipped to > -H)
     int32_t qy_hi;     // largest row offset kept (clipped to < H)
-    int32_t cap;       // capacity of one column run
+    int32_t cap;       // stride of one column run: a multiple of 8, zero-padded
     int32_t pad;
     int64_t col_off;   // index of this trajectory's first column record
     int64_t val_off;   // index of this trajectory's first K value

@@ -289,7 +289,7 @@ __global__ void k_trail(int T, int S, const int32_t *__restrict__ tab32,
         }
         colmeta[ti.col_off + c] = make_int2(lo, len);
         double *kv = kvals + ti.val_off + (int64_t)c * ti.cap;
-        for (int i = 0; i < len; ++i)
+        for (int i = 0; i < ti.cap; ++i)   // the zero tail pads runs to whole chunks
             kv[i] = 0.0;
         if (len == 0)
             continue;
@@ -325,12 +325,15 @@ hipError_t launch_trail(hipStream_t st, int J, int T, int S, int H, const int32_
 // ------------------------------------------------------------------ k_lambda (FP64)
 
 // Lam_j(y, x) = sum over trail columns qx, rows qy of K_j(qy, qx) ivar(y+qy, x+qx).
-// A lane owns one column x and 8 consecutive rows; per trail column it walks a
-// register window down the image column so that each ivar load serves up to 8
-// outputs.  The K values are uniform across the wave (scalar loads).
+// A lane owns one image column x and 8 consecutive rows.  Each trail column's
+// run is zero-padded to whole chunks of 8 values; per chunk the 8 K values are
+// wave-uniform (one scalar load) and a sliding window of 15 ivar values down
+// the image column feeds 64 branch-free FP64 FMAs, each ivar load serving up
+// to 8 outputs.
 __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
 {
-    constexpr int R = 8;
+    constexpr int R = 8;    // outputs per lane
+    constexpr int C = 8;    // K values per chunk
     int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.n_items)
         return;
@@ -353,17 +356,31 @@ __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
         const int X = x + ti.qx0 + c;
         const bool xin = (unsigned)X < (unsigned)a.W;
         const double *kv = a.kvals + ti.val_off + (int64_t)c * ti.cap;
-        for (int i = 0; i < len + R - 1; ++i) {
-            const int Y = y0 + m.x + i;
-            double v = 0.0;
-            if (xin && (unsigned)Y < (unsigned)a.H)
-                v = a.ivar64[(size_t)Y * a.W + X];
+        const int ybase = y0 + m.x;
+        double v[R + C - 1];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int q = i - r;
-                if (q >= 0 && q < len)
-                    acc[r] = fma(kv[q], v, acc[r]);
+        for (int i = 0; i < R - 1; ++i) {
+            const int Y = ybase + i;
+            v[i] = (xin && (unsigned)Y < (unsigned)a.H) ? a.ivar64[(size_t)Y * a.W + X] : 0.0;
+        }
+        for (int q0 = 0; q0 < len; q0 += C) {
+#pragma unroll
+            for (int i = R - 1; i < R + C - 1; ++i) {
+                const int Y = ybase + q0 + i;
+                v[i] = (xin && (unsigned)Y < (unsigned)a.H) ? a.ivar64[(size_t)Y * a.W + X] : 0.0;
             }
+            double kc[C];
+#pragma unroll
+            for (int t = 0; t < C; ++t)
+                kc[t] = kv[q0 + t];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int t = 0; t < C; ++t)
+                    acc[r] = fma(kc[t], v[t + r], acc[r]);
+#pragma unroll
+            for (int i = 0; i < R - 1; ++i)
+                v[i] = v[i + C];
         }
     }
     if (x < a.W) {
@@ -384,26 +401,32 @@ hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a)
 
 // ------------------------------------------------------------------ k_search
 
-// One block = one (tile of 128x32 start pixels, trajectory).  Per frame k the
-// block stages the window the tile's stamps cover at the frame's integer
-// shift -- (32+S-1) rows x (128+S-1) columns of Z -- into LDS with aligned
-// float4 loads (the sub-float4 offset d is applied when reading), then every
+// One block = one (tile of 128 x SEARCH_TY start pixels, trajectory).  Per
+// frame k the block needs the window of Z its stamps cover at the frame's
+// integer shift: (TY+S-1) rows x (128+S-1) columns, staged as aligned float4
+// groups (the sub-float4 offset d is applied when reading).  The window of
+// frame k+1 is fetched into registers before frame k is computed and stored
+// into the other half of a double-buffered LDS window afterwards, so global
+// latency overlaps the arithmetic and one barrier per frame suffices.  Every
 // lane evaluates the separable stamp for its 2 columns x 8 rows: a horizontal
-// pass of S taps per window row, streamed into a vertical pass of S taps.
-// The PRF taps and shift are wave-uniform (scalar loads of the table entry).
-// Frame partials accumulate in FP32 over FRAME_CHUNK frames, then into FP64.
+// pass of S taps per window row streamed into a vertical pass of S taps.  The
+// table entry (shift, PRF taps) is wave-uniform (scalar loads).  Frame
+// partials accumulate in FP32 over FRAME_CHUNK frames, then into FP64.
 template <int S>
 __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a)
 {
     constexpr int h = S / 2;
-    constexpr int CPL = 2, RPL = 8;
+    constexpr int CPL = 2, RPL = SEARCH_RPL;
+    constexpr int NT = SEARCH_THREADS;
     constexpr int TX = SEARCH_TX, TY = SEARCH_TY;
     constexpr int WY = TY + S - 1;
     constexpr int NG = (TX + S - 1 + 3 + 3) / 4;
     constexpr int LS = NG * 4;
+    constexpr int NWIN = WY * NG;
+    constexpr int NLD = (NWIN + NT - 1) / NT;
     constexpr int TS = table_stride(S);
     constexpr int NV = CPL + S - 1;
-    __shared__ float4 win4[WY * NG];
+    __shared__ float4 win4[2][NWIN];
 
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.n_items)
@@ -412,8 +435,57 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a)
     const int tile = item / a.J;
     const int tyi = tile / a.ntx, txi = tile - tyi * a.ntx;
     const int ty0 = tyi * TY, tx0 = txi * TX;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const float *win = reinterpret_cast<const float *>(win4);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+
+    // This thread's staging slots: window group idx = tid + NT*it at (row r,
+    // group g), global offset r * Wp4 + g from the window origin.
+    int soff[NLD];
+#pragma unroll
+    for (int it = 0; it < NLD; ++it) {
+        const int idx = tid + NT * it;
+        const int r = idx / NG;
+        soff[it] = r * a.Wp4 + (idx - r * NG);
+    }
+    // only the last slot can fall past the window
+    const bool last_ok = tid + NT * (NLD - 1) < NWIN;
+
+    const int32_t *tabj = a.tab32 + (size_t)j * a.T * TS;
+    const size_t frame4 = (size_t)a.Hp * a.Wp4;
+
+    // Fetch the window of frame k into registers; returns its sub-float4 offset.
+    auto fetch = [&](int k, float4 (&pre)[NLD]) -> int {
+        const int32_t *e = tabj + (size_t)k * TS;
+        const int oy = ty0 + e[0] - h + a.Pt;
+        const int ox = tx0 + e[1] - h + a.Pl;
+        const int ag = ox >> 2;      // floor division (arithmetic shift)
+        const float4 *Zk = a.Z4 + (size_t)k * frame4;
+        if (oy >= 0 && oy + WY <= a.Hp && ag >= 0 && ag + NG <= a.Wp4) {
+            const float4 *b = Zk + (size_t)oy * a.Wp4 + ag;
+#pragma unroll
+            for (int it = 0; it < NLD; ++it)
+                if (it < NLD - 1 || last_ok)
+                    pre[it] = b[soff[it]];
+        } else {
+#pragma unroll
+            for (int it = 0; it < NLD; ++it) {
+                const int idx = tid + NT * it;
+                const int r = idx / NG;
+                const int yp = oy + r, gp = ag + (idx - r * NG);
+                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (idx < NWIN && (unsigned)yp < (unsigned)a.Hp && (unsigned)gp < (unsigned)a.Wp4)
+                    v = Zk[(size_t)yp * a.Wp4 + gp];
+                pre[it] = v;
+            }
+        }
+        return ox - (ag << 2);
+    };
+    auto store = [&](int buf, const float4 (&pre)[NLD]) {
+#pragma unroll
+        for (int it = 0; it < NLD; ++it)
+            if (it < NLD - 1 || last_ok)
+                win4[buf][tid + NT * it] = pre[it];
+    };
 
     float part[RPL][CPL];
     double acc[RPL][CPL];
@@ -425,34 +497,25 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a)
             acc[o][c] = 0.0;
         }
 
-    const int32_t *tabj = a.tab32 + (size_t)j * a.T * TS;
-    const size_t frame4 = (size_t)a.Hp * a.Wp4;
+    float4 pre[NLD];
+    int d_cur = fetch(0, pre);
+    store(0, pre);
+    __syncthreads();
     for (int k = 0; k < a.T; ++k) {
+        const int buf = k & 1;
+        int d_next = 0;
+        if (k + 1 < a.T)
+            d_next = fetch(k + 1, pre);
+
         const int32_t *e = tabj + (size_t)k * TS;
-        const int iy = e[0], ix = e[1];
         float gy[S], gx[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             gy[s] = __int_as_float(e[2 + s]);
             gx[s] = __int_as_float(e[2 + S + s]);
         }
-        const int oy = ty0 + iy - h + a.Pt;
-        const int ox = tx0 + ix - h + a.Pl;
-        const int ag = ox >> 2;          // floor division (arithmetic shift)
-        const int d = ox - (ag << 2);    // 0..3
-        const float4 *Zk = a.Z4 + (size_t)k * frame4;
-        for (int idx = threadIdx.x; idx < WY * NG; idx += SEARCH_THREADS) {
-            const int r = idx / NG;
-            const int g = idx - r * NG;
-            const int yp = oy + r, gp = ag + g;
-            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if ((unsigned)yp < (unsigned)a.Hp && (unsigned)gp < (unsigned)a.Wp4)
-                v = Zk[(size_t)yp * a.Wp4 + gp];
-            win4[idx] = v;
-        }
-        __syncthreads();
-
-        const float *base = win + (wv * RPL) * LS + CPL * lane + d;
+        const float *base = reinterpret_cast<const float *>(win4[buf]) + (wv * RPL) * LS +
+                            CPL * lane + d_cur;
 #pragma unroll
         for (int rr = 0; rr < RPL + S - 1; ++rr) {
             float v[NV];
@@ -462,11 +525,11 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a)
             float hs[CPL];
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                float s = gx[0] * v[c];
+                float sum = gx[0] * v[c];
 #pragma unroll
                 for (int b = 1; b < S; ++b)
-                    s = fmaf(gx[b], v[c + b], s);
-                hs[c] = s;
+                    sum = fmaf(gx[b], v[c + b], sum);
+                hs[c] = sum;
             }
 #pragma unroll
             for (int aa = 0; aa < S; ++aa) {
@@ -478,7 +541,10 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a)
                 }
             }
         }
+        if (k + 1 < a.T)
+            store(buf ^ 1, pre);
         __syncthreads();
+        d_cur = d_next;
         if ((k % FRAME_CHUNK) == FRAME_CHUNK - 1) {
 #pragma unroll
             for (int o = 0; o < RPL; ++o)
@@ -525,13 +591,13 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a)
         uint64_t o = __shfl_xor(best, off, 64);
         best = o > best ? o : best;
     }
-    __shared__ uint64_t wbest[SEARCH_THREADS / 64];
+    __shared__ uint64_t wbest[SEARCH_WAVES];
     if (lane == 0)
         wbest[wv] = best;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         uint64_t m = wbest[0];
-        for (int w = 1; w < SEARCH_THREADS / 64; ++w)
+        for (int w = 1; w < SEARCH_WAVES; ++w)
             m = wbest[w] > m ? wbest[w] : m;
         a.tile_keys[(size_t)j * (a.ntx * a.nty) + tile] = m;
     }

@@ -201,7 +201,7 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
             if (c < (double)cap)
                 cap = (int)c;
         }
-        ti.cap = std::max(cap, 1);
+        ti.cap = (int)align_up((size_t)std::max(cap, 1), 8);   // whole chunks of 8
         ti.col_off = coff;
         ti.val_off = voff;
         coff += ti.ncols;
