@@ -66,7 +66,8 @@ struct LambdaArgs {
 
 // ---- launch wrappers (all on `st`; return hipError_t of the launch)
 hipError_t launch_zero(hipStream_t st, int32_t *p, int n);
-hipError_t launch_ivar(hipStream_t st, int HW, const float *sigma, float *ivar32, double *ivar64);
+hipError_t launch_ivar(hipStream_t st, int HW, const float *sigma, float *ivar32, double *ivar64,
+                       int32_t *err);
 hipError_t launch_prep_z(hipStream_t st, int dtype, const void *R, const float *scales,
                          const float *ivar32, float4 *Z4, int T, int H, int W, int Hp, int Wp4,
                          int Pt, int Pl);

@@ -69,21 +69,25 @@ hipError_t launch_zero(hipStream_t st, int32_t *p, int n)
 // ------------------------------------------------------------------ k_ivar
 
 __global__ void k_ivar(int HW, const float *__restrict__ sigma, float *__restrict__ ivar32,
-                       double *__restrict__ ivar64)
+                       double *__restrict__ ivar64, int32_t *__restrict__ err)
 {
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += gridDim.x * blockDim.x) {
         double s = (double)sigma[p];
         double iv = (__builtin_isfinite(s) && s > 0.0) ? 1.0 / (s * s) : 0.0;
+        float iv32 = (float)iv;
+        if (!__builtin_isfinite(iv32))
+            atomicOr(err, 2);     // 1/sigma^2 beyond single precision: rejected
         ivar64[p] = iv;
-        ivar32[p] = (float)iv;
+        ivar32[p] = iv32;
     }
 }
 
-hipError_t launch_ivar(hipStream_t st, int HW, const float *sigma, float *ivar32, double *ivar64)
+hipError_t launch_ivar(hipStream_t st, int HW, const float *sigma, float *ivar32, double *ivar64,
+                       int32_t *err)
 {
     int blocks = (HW + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_ivar, dim3(blocks), dim3(256), 0, st, HW, sigma, ivar32, ivar64);
+    hipLaunchKernelGGL(k_ivar, dim3(blocks), dim3(256), 0, st, HW, sigma, ivar32, ivar64, err);
     return hipGetLastError();
 }
 
@@ -134,7 +138,43 @@ __global__ void k_prep_z(const void *__restrict__ R, const float *__restrict__ s
     int k = blockIdx.z;
     int y = yp - Pt;
     int nqy = (H + TNO_QTILE - 1) / TNO_QTILE, nqx = (W + TNO_QTILE - 1) / TNO_QTILE;
+    const int x0 = 4 * g - Pl;        // Pl is a multiple of 4
     float v[4];
+    if ((W & 3) == 0 && y >= 0 && y < H && x0 >= 0 && x0 + 3 < W) {
+        // whole group inside the image and 4-aligned: vector loads
+        const size_t p = (size_t)y * W + x0;
+        const size_t i = (size_t)k * H * W + p;
+        const float4 iv = *reinterpret_cast<const float4 *>(ivar32 + p);
+        float r[4];
+        if constexpr (DT == TNO_F32) {
+            const float4 rv = *reinterpret_cast<const float4 *>((const float *)R + i);
+            r[0] = rv.x; r[1] = rv.y; r[2] = rv.z; r[3] = rv.w;
+        } else {
+            const float s = scales[((size_t)k * nqy + (y >> 6)) * nqx + (x0 >> 6)];
+            if constexpr (DT == TNO_FP8_E4M3) {
+                const uint32_t c4 = *reinterpret_cast<const uint32_t *>((const uint8_t *)R + i);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    r[e] = decode_e4m3((c4 >> (8 * e)) & 0xFFu) * (s * 256.0f);
+            } else {
+                const uint2 c2 = *reinterpret_cast<const uint2 *>((const uint16_t *)R + i);
+                const uint32_t c[4] = {c2.x & 0xFFFFu, c2.x >> 16, c2.y & 0xFFFFu, c2.y >> 16};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if constexpr (DT == TNO_BF16) {
+                        r[e] = __uint_as_float(c[e] << 16) * s;
+                    } else {
+                        uint16_t hb = (uint16_t)c[e];
+                        _Float16 hv;
+                        __builtin_memcpy(&hv, &hb, 2);
+                        r[e] = (float)hv * s;
+                    }
+                }
+            }
+        }
+        Z4[((size_t)k * Hp + yp) * Wp4 + g] = make_float4(r[0] * iv.x, r[1] * iv.y, r[2] * iv.z, r[3] * iv.w);
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         int x = 4 * g + e - Pl;

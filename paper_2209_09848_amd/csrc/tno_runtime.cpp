@@ -1,11 +1,13 @@
 // tno_runtime.cpp -- host side of the C ABI declared in include/tno_search.h.
 //
-// Responsibilities: argument validation, the per-request plan (shift bounds,
-// padding of the staged stack, trail-kernel layout, tiling, footprint),
-// admission against an HBM budget and an in-flight limit, one device arena
-// per request, the kernel sequence on the handle's stream, and ticketed
-// completion with HIP events.  Validation and planning touch no GPU and back
-// the host-only helpers tno_search_validate / tno_search_footprint.
+// Responsibilities: argument validation; the per-request plan (shift bounds,
+// padding of the staged stack, trail-kernel layout, tiling, footprint);
+// admission against an HBM budget and an in-flight limit; resident residual
+// stacks keyed by stack_key with LRU eviction; one device arena per request
+// from a block cache; a pool of HIP streams so that concurrently admitted
+// requests overlap on the device; the kernel sequence of a request on its
+// stream; ticketed completion with HIP events.  Validation and planning touch
+// no GPU and back the host-only helpers tno_search_validate / footprint.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -77,6 +79,8 @@ struct Plan {
     int lntx = 0, lnty = 0;
     int64_t N = 0, n_chunks = 0;
     bool own_snr = true, own_flux = true;
+    bool stack_in_arena = false;      // host residuals copied into the arena (no stack_key)
+    size_t stack_bytes = 0;           // bytes of a resident stack holding these residuals
     // arena layout (byte offsets)
     size_t o_R = 0, o_scales = 0, o_sigma = 0, o_times = 0, o_vel = 0, o_Z = 0, o_iv32 = 0,
            o_iv64 = 0, o_tab32 = 0, o_tab64 = 0, o_trail = 0, o_colmeta = 0, o_kvals = 0,
@@ -237,11 +241,17 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
         off = align_up(off + std::max<size_t>(bytes, 1), ALIGN);
         return at;
     };
-    if (!p.dev) {
+    const size_t scale_bytes = p.dtype == TNO_F32 ? 0 : T * ((H + 63) / 64) * ((W + 63) / 64) * 4;
+    p.stack_bytes = align_up(T * HW * elem_bytes(p.dtype), ALIGN) + align_up(scale_bytes, ALIGN) +
+                    align_up(HW * 4, ALIGN);
+    p.stack_in_arena = !p.dev && r->stack_key == 0;
+    if (p.stack_in_arena) {
         p.o_R = take(T * HW * elem_bytes(p.dtype));
-        if (p.dtype != TNO_F32)
-            p.o_scales = take(T * ((H + 63) / 64) * ((W + 63) / 64) * 4);
+        if (scale_bytes)
+            p.o_scales = take(scale_bytes);
         p.o_sigma = take(HW * 4);
+    }
+    if (!p.dev) {
         p.o_times = take(T * 8);
         p.o_vel = take(J * 16);
     }
@@ -271,12 +281,28 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     return fail(TNO_OK, "");
 }
 
+// A residual stack kept on the device under a caller's stack_key: codes or
+// FP32 residuals, tile scales, sigma.  Requests reference it while in flight.
+struct Stack {
+    uint64_t key = 0;
+    int H = 0, W = 0, T = 0, dtype = 0;
+    void *block = nullptr;
+    size_t block_bytes = 0;
+    size_t bytes = 0;          // bytes counted against the budget
+    size_t o_R = 0, o_scales = 0, o_sigma = 0;
+    int refs = 0;
+    uint64_t last_use = 0;
+    hipEvent_t ready = nullptr;
+};
+
 struct Request {
     uint64_t ticket = 0;
     Plan plan;
     tno_outputs out{};
     void *arena = nullptr;
     size_t arena_bytes = 0;
+    Stack *stack = nullptr;
+    hipStream_t stream = nullptr;
     hipEvent_t ev[6] = {};   // phase boundaries; ev[0] start, ev[5] end
     std::chrono::steady_clock::time_point t_submit;
     uint64_t updates = 0;
@@ -319,16 +345,21 @@ struct ArenaCache {
 
 }  // namespace
 
+constexpr int STREAM_POOL = 4;   // at the default priority
+
 struct tno_search {
     int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
+    std::vector<hipStream_t> streams;
+    bool own_streams = false;
+    unsigned next_stream = 0;
     uint64_t budget = 0;
-    uint64_t in_use = 0;
+    uint64_t in_use = 0;               // live arenas + resident stacks
     int max_inflight = 64;
     uint64_t next_ticket = 1;
+    uint64_t tick = 0;
     std::mutex mu;
     std::map<uint64_t, Request *> live;
+    std::map<uint64_t, Stack *> stacks;
     ArenaCache cache;
 };
 
@@ -346,18 +377,87 @@ int hip_fail(hipError_t e, const char *what, char *msg, size_t n)
 
 template <class T> T *at(void *arena, size_t off) { return (T *)((char *)arena + off); }
 
-// Enqueue the whole search of one request on the handle's stream.
-hipError_t enqueue(tno_search *hd, Request *q, const tno_request *r)
+// Make `need` bytes of budget available: evict idle resident stacks (least
+// recently used first), then shrink the block cache so that live memory plus
+// cached blocks stay within the budget.  Returns false if it cannot.
+bool make_room(tno_search *h, size_t need)
+{
+    while (h->in_use + need > h->budget) {
+        Stack *victim = nullptr;
+        for (auto &kv : h->stacks)
+            if (kv.second->refs == 0 && (!victim || kv.second->last_use < victim->last_use))
+                victim = kv.second;
+        if (!victim)
+            return false;
+        h->stacks.erase(victim->key);
+        h->cache.put(victim->block, victim->block_bytes);
+        h->in_use -= victim->bytes;
+        if (victim->ready)
+            (void)hipEventDestroy(victim->ready);
+        delete victim;
+    }
+    h->cache.trim(h->budget - h->in_use - need);
+    return true;
+}
+
+// A device block of at least `bytes` from the cache, else hipMalloc.
+void *get_block(tno_search *h, size_t bytes, size_t *got)
+{
+    void *p = h->cache.take(bytes, got);
+    if (p)
+        return p;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        h->cache.trim(0);
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    *got = bytes;
+    return p;
+}
+
+struct Inputs {
+    const void *R;
+    const float *scales;
+    const float *sigma;
+    const double *times;
+    const double *vel;
+};
+
+Inputs inputs_of(const Request *q, const tno_request *r)
 {
     const Plan &p = q->plan;
-    hipStream_t st = hd->stream;
     void *A = q->arena;
-    const void *R = p.dev ? r->residuals : at<void>(A, p.o_R);
-    const float *scales = p.dtype == TNO_F32 ? nullptr
-                          : (p.dev ? r->tile_scales : at<float>(A, p.o_scales));
-    const float *sigma = p.dev ? r->sigma : at<float>(A, p.o_sigma);
-    const double *times = p.dev ? r->times : at<double>(A, p.o_times);
-    const double *vel = p.dev ? r->velocities : at<double>(A, p.o_vel);
+    Inputs in;
+    if (q->stack) {
+        void *B = q->stack->block;
+        in.R = at<void>(B, q->stack->o_R);
+        in.scales = p.dtype == TNO_F32 ? nullptr : at<float>(B, q->stack->o_scales);
+        in.sigma = at<float>(B, q->stack->o_sigma);
+    } else if (p.stack_in_arena) {
+        in.R = at<void>(A, p.o_R);
+        in.scales = p.dtype == TNO_F32 ? nullptr : at<float>(A, p.o_scales);
+        in.sigma = at<float>(A, p.o_sigma);
+    } else {
+        in.R = r->residuals;
+        in.scales = p.dtype == TNO_F32 ? nullptr : r->tile_scales;
+        in.sigma = r->sigma;
+    }
+    in.times = p.dev ? r->times : at<double>(A, p.o_times);
+    in.vel = p.dev ? r->velocities : at<double>(A, p.o_vel);
+    return in;
+}
+
+// Enqueue the whole search of one request on its stream.
+hipError_t enqueue(tno_search *hd, Request *q, const tno_request *r)
+{
+    (void)hd;
+    const Plan &p = q->plan;
+    hipStream_t st = q->stream;
+    void *A = q->arena;
+    const Inputs in = inputs_of(q, r);
     float *snr = p.own_snr ? at<float>(A, p.o_snr) : q->out.snr;
     float *flux = p.own_flux ? at<float>(A, p.o_flux) : q->out.flux;
     const int HW = p.H * p.W;
@@ -368,15 +468,18 @@ hipError_t enqueue(tno_search *hd, Request *q, const tno_request *r)
         if (e != hipSuccess)    \
             return e;           \
     } while (0)
+    if (q->stack && q->stack->ready)
+        TRY(hipStreamWaitEvent(st, q->stack->ready, 0));
     TRY(hipEventRecord(q->ev[0], st));
     TRY(tno::launch_zero(st, at<int32_t>(A, p.o_err), 1));
     TRY(hipMemcpyAsync(at<void>(A, p.o_trail), p.trail.data(), p.trail.size() * sizeof(tno::TrailInfo),
                        hipMemcpyHostToDevice, st));
-    TRY(tno::launch_ivar(st, HW, sigma, at<float>(A, p.o_iv32), at<double>(A, p.o_iv64)));
-    TRY(tno::launch_prep_z(st, p.dtype, R, scales, at<float>(A, p.o_iv32), at<float4>(A, p.o_Z), p.T,
-                           p.H, p.W, p.Hp, p.Wp4, p.Pt, p.Pl));
+    TRY(tno::launch_ivar(st, HW, in.sigma, at<float>(A, p.o_iv32), at<double>(A, p.o_iv64),
+                         at<int32_t>(A, p.o_err)));
+    TRY(tno::launch_prep_z(st, p.dtype, in.R, in.scales, at<float>(A, p.o_iv32), at<float4>(A, p.o_Z),
+                           p.T, p.H, p.W, p.Hp, p.Wp4, p.Pt, p.Pl));
     TRY(hipEventRecord(q->ev[1], st));
-    TRY(tno::launch_table(st, p.J, p.T, times, p.t_ref, vel, p.kind, p.sigma_px, p.S,
+    TRY(tno::launch_table(st, p.J, p.T, in.times, p.t_ref, in.vel, p.kind, p.sigma_px, p.S,
                           at<int32_t>(A, p.o_tab32), at<double>(A, p.o_tab64)));
     TRY(tno::launch_trail(st, p.J, p.T, p.S, p.H, at<int32_t>(A, p.o_tab32), at<double>(A, p.o_tab64),
                           at<tno::TrailInfo>(A, p.o_trail), at<int2>(A, p.o_colmeta),
@@ -442,12 +545,17 @@ hipError_t enqueue(tno_search *hd, Request *q, const tno_request *r)
 
 void release(tno_search *hd, Request *q)
 {
-    if (q->arena)
+    if (q->arena) {
         hd->cache.put(q->arena, q->arena_bytes);
+        hd->in_use -= q->plan.bytes;
+    }
+    if (q->stack) {
+        q->stack->refs -= 1;
+        q->stack->last_use = ++hd->tick;
+    }
     for (hipEvent_t &e : q->ev)
         if (e)
             (void)hipEventDestroy(e);
-    hd->in_use -= q->plan.bytes;
     delete q;
 }
 
@@ -497,7 +605,9 @@ uint64_t tno_search_footprint(const tno_request *req, const tno_outputs *out)
         return 0;
     Plan p;
     Fail f = make_plan(req, out, req->times, req->velocities, p);
-    return f.code == TNO_OK ? (uint64_t)p.bytes : 0;
+    if (f.code != TNO_OK)
+        return 0;
+    return (uint64_t)p.bytes + (req->stack_key ? p.stack_bytes : 0);
 }
 
 const char *tno_search_last_error(void) { return g_last_error; }
@@ -528,18 +638,25 @@ int tno_search_create(const tno_config *cfg, tno_search **out_handle)
     h->device = cfg->device;
     h->max_inflight = cfg->max_inflight > 0 ? cfg->max_inflight : 64;
     if (cfg->stream) {
-        h->stream = (hipStream_t)cfg->stream;
+        h->streams.push_back((hipStream_t)cfg->stream);
     } else {
-        if ((e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking)) != hipSuccess) {
-            delete h;
-            return hip_fail(e, "hipStreamCreate", nullptr, 0);
+        h->own_streams = true;
+        for (int i = 0; i < STREAM_POOL; ++i) {
+            hipStream_t s = nullptr;
+            if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) {
+                for (hipStream_t t : h->streams)
+                    (void)hipStreamDestroy(t);
+                delete h;
+                return hip_fail(e, "hipStreamCreate", nullptr, 0);
+            }
+            h->streams.push_back(s);
         }
-        h->own_stream = true;
     }
     size_t fr = 0, tot = 0;
     if ((e = hipMemGetInfo(&fr, &tot)) != hipSuccess) {
-        if (h->own_stream)
-            (void)hipStreamDestroy(h->stream);
+        if (h->own_streams)
+            for (hipStream_t t : h->streams)
+                (void)hipStreamDestroy(t);
         delete h;
         return hip_fail(e, "hipMemGetInfo", nullptr, 0);
     }
@@ -560,15 +677,31 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
         set_last(f);
         return f.code;
     }
-    if (!req->residuals) {
-        set_last(fail(TNO_E_INVAL, "stack_key %llu is not resident", (unsigned long long)req->stack_key));
-        return TNO_E_INVAL;
-    }
     std::lock_guard<std::mutex> lock(h->mu);
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess)
         return hip_fail(e, "hipSetDevice", nullptr, 0);
     const bool dev = (req->flags & TNO_REQ_DEVICE_PTRS) != 0;
+
+    // resident stack lookup
+    Stack *st = nullptr;
+    if (req->stack_key) {
+        auto it = h->stacks.find(req->stack_key);
+        if (it != h->stacks.end()) {
+            st = it->second;
+            if (st->H != req->height || st->W != req->width || st->T != req->n_frames ||
+                st->dtype != req->dtype) {
+                set_last(fail(TNO_E_INVAL, "stack_key %llu is resident with another shape or dtype",
+                              (unsigned long long)req->stack_key));
+                return TNO_E_INVAL;
+            }
+        }
+    }
+    if (!st && !req->residuals) {
+        set_last(fail(TNO_E_INVAL, "stack_key %llu is not resident", (unsigned long long)req->stack_key));
+        return TNO_E_INVAL;
+    }
+
     std::vector<double> times_h, vel_h;
     const double *times = req->times, *vel = req->velocities;
     if (dev) {
@@ -592,49 +725,46 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
         return f.code;
     }
     const Plan &p = q->plan;
-    if (p.bytes > h->budget) {
+    const bool new_stack = req->stack_key && !st;
+    const size_t need = p.bytes + (new_stack ? p.stack_bytes : 0);
+    if (need > h->budget) {
         delete q;
-        set_last(fail(TNO_E_NOMEM, "request needs %.3g GB, budget is %.3g GB", p.bytes / 1e9, h->budget / 1e9));
+        set_last(fail(TNO_E_NOMEM, "request needs %.3g GB, budget is %.3g GB", need / 1e9, h->budget / 1e9));
         return TNO_E_NOMEM;
     }
-    if ((int)h->live.size() >= h->max_inflight || h->in_use + p.bytes > h->budget) {
+    if (st)
+        st->refs += 1;   // pin before making room so it cannot be evicted
+    if ((int)h->live.size() >= h->max_inflight || !make_room(h, need)) {
+        if (st)
+            st->refs -= 1;
         delete q;
         set_last(fail(TNO_E_BUSY, "in-flight limit or HBM budget reached"));
         return TNO_E_BUSY;
     }
-    if (req->flags & TNO_REQ_VALIDATE) {
-        // scan host residuals and sigma for non-finite values (device inputs are
-        // scanned after staging by the same rule: non-finite residuals are rejected)
-        if (!dev && req->dtype == TNO_F32) {
-            const float *Rh = (const float *)req->residuals;
-            size_t n = (size_t)p.T * p.H * p.W;
-            for (size_t i = 0; i < n; ++i)
-                if (!std::isfinite(Rh[i])) {
-                    delete q;
-                    set_last(fail(TNO_E_INVAL, "residual %zu is not finite", i));
-                    return TNO_E_INVAL;
-                }
-        }
+    if ((req->flags & TNO_REQ_VALIDATE) && !dev && req->dtype == TNO_F32 && req->residuals) {
+        const float *Rh = (const float *)req->residuals;
+        size_t n = (size_t)p.T * p.H * p.W;
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(Rh[i])) {
+                if (st)
+                    st->refs -= 1;
+                delete q;
+                set_last(fail(TNO_E_INVAL, "residual %zu is not finite", i));
+                return TNO_E_INVAL;
+            }
     }
     q->out = *out;
     q->t_submit = std::chrono::steady_clock::now();
     q->updates = (uint64_t)p.J * p.H * p.W * p.T;
-    q->arena = h->cache.take(p.bytes, &q->arena_bytes);
+    q->stream = h->streams[h->next_stream++ % h->streams.size()];
+    q->stack = st;
+    q->arena = get_block(h, p.bytes, &q->arena_bytes);
     if (!q->arena) {
-        // make room: cached blocks count against the budget
-        h->cache.trim(h->budget > h->in_use + p.bytes ? h->budget - h->in_use - p.bytes : 0);
-        if ((e = hipMalloc(&q->arena, p.bytes)) != hipSuccess) {
-            (void)hipGetLastError();
-            h->cache.trim(0);
-            if ((e = hipMalloc(&q->arena, p.bytes)) != hipSuccess) {
-                (void)hipGetLastError();
-                q->arena = nullptr;
-                delete q;
-                set_last(fail(TNO_E_NOMEM, "hipMalloc of %.3g GB failed", p.bytes / 1e9));
-                return TNO_E_NOMEM;
-            }
-        }
-        q->arena_bytes = p.bytes;
+        if (st)
+            st->refs -= 1;
+        delete q;
+        set_last(fail(TNO_E_NOMEM, "device allocation of %.3g GB failed", p.bytes / 1e9));
+        return TNO_E_NOMEM;
     }
     h->in_use += p.bytes;
     for (hipEvent_t &ev : q->ev)
@@ -642,19 +772,67 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
             release(h, q);
             return hip_fail(e, "hipEventCreate", nullptr, 0);
         }
+    const size_t HW = (size_t)p.H * p.W;
+    const size_t rbytes = (size_t)p.T * HW * elem_bytes(p.dtype);
+    const size_t sbytes = p.dtype == TNO_F32 ? 0 : (size_t)p.T * ((p.H + 63) / 64) * ((p.W + 63) / 64) * 4;
+    if (new_stack) {
+        // keep these residuals on the device under the caller's key
+        Stack *ns = new (std::nothrow) Stack();
+        size_t got = 0;
+        void *blk = ns ? get_block(h, p.stack_bytes, &got) : nullptr;
+        if (!blk) {
+            delete ns;
+            release(h, q);
+            set_last(fail(TNO_E_NOMEM, "device allocation of a %.3g GB stack failed", p.stack_bytes / 1e9));
+            return TNO_E_NOMEM;
+        }
+        ns->key = req->stack_key;
+        ns->H = p.H;
+        ns->W = p.W;
+        ns->T = p.T;
+        ns->dtype = p.dtype;
+        ns->block = blk;
+        ns->block_bytes = got;
+        ns->bytes = p.stack_bytes;
+        ns->o_R = 0;
+        ns->o_scales = align_up(rbytes, ALIGN);
+        ns->o_sigma = ns->o_scales + align_up(sbytes, ALIGN);
+        const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        if ((e = hipEventCreate(&ns->ready)) == hipSuccess &&
+            (e = hipMemcpyAsync(at<void>(blk, ns->o_R), req->residuals, rbytes, kind, q->stream)) == hipSuccess &&
+            (!sbytes || (e = hipMemcpyAsync(at<void>(blk, ns->o_scales), req->tile_scales, sbytes, kind,
+                                            q->stream)) == hipSuccess) &&
+            (e = hipMemcpyAsync(at<void>(blk, ns->o_sigma), req->sigma, HW * 4, kind, q->stream)) == hipSuccess &&
+            (e = hipEventRecord(ns->ready, q->stream)) == hipSuccess) {
+            if (!dev)
+                e = hipStreamSynchronize(q->stream);   // host inputs are read before submit returns
+        }
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(q->stream);
+            if (ns->ready)
+                (void)hipEventDestroy(ns->ready);
+            h->cache.put(blk, got);
+            delete ns;
+            release(h, q);
+            return hip_fail(e, "staging a resident stack", nullptr, 0);
+        }
+        ns->refs = 1;
+        ns->last_use = ++h->tick;
+        h->stacks[ns->key] = ns;
+        h->in_use += ns->bytes;
+        q->stack = ns;
+    }
     if (!dev) {
         // host inputs are copied before submit returns
-        const size_t HW = (size_t)p.H * p.W;
         void *A = q->arena;
         struct {
             size_t off;
             const void *src;
             size_t bytes;
         } cps[] = {
-            {p.o_R, req->residuals, (size_t)p.T * HW * elem_bytes(p.dtype)},
-            {p.o_scales, req->tile_scales,
-             p.dtype == TNO_F32 ? 0 : (size_t)p.T * ((p.H + 63) / 64) * ((p.W + 63) / 64) * 4},
-            {p.o_sigma, req->sigma, HW * 4},
+            {p.o_R, req->residuals, p.stack_in_arena ? rbytes : 0},
+            {p.o_scales, req->tile_scales, p.stack_in_arena ? sbytes : 0},
+            {p.o_sigma, req->sigma, p.stack_in_arena ? HW * 4 : 0},
             {p.o_times, req->times, (size_t)p.T * 8},
             {p.o_vel, req->velocities, (size_t)p.J * 16},
         };
@@ -665,7 +843,7 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
             }
     }
     if ((e = enqueue(h, q, req)) != hipSuccess) {
-        (void)hipStreamSynchronize(h->stream);
+        (void)hipStreamSynchronize(q->stream);
         release(h, q);
         return hip_fail(e, "enqueue", nullptr, 0);
     }
@@ -708,14 +886,18 @@ int tno_search_poll(tno_search *h, uint64_t ticket, int32_t timeout_ms, tno_resu
                         *ph[i] = ms;
                 int32_t err = 0;
                 hipError_t e2 = hipMemcpy(&err, at<void>(q->arena, q->plan.o_err), 4, hipMemcpyDeviceToHost);
-                if (e2 == hipSuccess)
+                if (e2 == hipSuccess && !err)
                     e2 = finish_outputs(q);
                 if (e2 != hipSuccess) {
                     res.status = TNO_E_DEVICE;
                     snprintf(res.message, sizeof res.message, "%s", hipGetErrorString(e2));
-                } else if (err) {
+                } else if (err & 1) {
                     res.status = TNO_E_INTERNAL;
                     snprintf(res.message, sizeof res.message, "trail run exceeded its planned capacity");
+                } else if (err & 2) {
+                    res.status = TNO_E_INVAL;
+                    snprintf(res.message, sizeof res.message,
+                             "sigma so small that 1/sigma^2 overflows single precision");
                 }
                 auto t1 = std::chrono::steady_clock::now();
                 res.total_ms = std::chrono::duration<double, std::milli>(t1 - q->t_submit).count();
@@ -730,7 +912,7 @@ int tno_search_poll(tno_search *h, uint64_t ticket, int32_t timeout_ms, tno_resu
                 memset(&res, 0, sizeof res);
                 res.status = TNO_E_DEVICE;
                 snprintf(res.message, sizeof res.message, "%s", hipGetErrorString(e));
-                (void)hipStreamSynchronize(h->stream);
+                (void)hipStreamSynchronize(q->stream);
                 h->live.erase(it);
                 release(h, q);
                 *out_result = res;
@@ -769,13 +951,22 @@ void tno_search_destroy(tno_search *h)
     {
         std::lock_guard<std::mutex> lock(h->mu);
         (void)hipSetDevice(h->device);
-        (void)hipStreamSynchronize(h->stream);
+        for (hipStream_t s : h->streams)
+            (void)hipStreamSynchronize(s);
         for (auto &kv : h->live)
             release(h, kv.second);
         h->live.clear();
+        for (auto &kv : h->stacks) {
+            h->cache.put(kv.second->block, kv.second->block_bytes);
+            if (kv.second->ready)
+                (void)hipEventDestroy(kv.second->ready);
+            delete kv.second;
+        }
+        h->stacks.clear();
         h->cache.trim(0);
-        if (h->own_stream)
-            (void)hipStreamDestroy(h->stream);
+        if (h->own_streams)
+            for (hipStream_t s : h->streams)
+                (void)hipStreamDestroy(s);
     }
     delete h;
 }

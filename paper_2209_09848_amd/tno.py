@@ -205,9 +205,14 @@ class Search:
     """One handle on torch's current stream of `device` (default cuda:0)."""
 
     def __init__(self, device: int = 0, max_inflight: int = 64, hbm_budget_bytes: int = 0,
-                 stream=None):
+                 stream=None, own_streams: bool = False):
+        """own_streams=True: the library runs requests on its own pool of streams
+        (concurrent requests overlap; inputs must be complete before submit);
+        otherwise every request runs on `stream` (default: torch's current)."""
         import torch
-        if stream is None:
+        if own_streams:
+            stream = 0
+        elif stream is None:
             stream = torch.cuda.current_stream(device).cuda_stream
         cfg = tno_config()
         cfg.device = device
@@ -215,7 +220,7 @@ class Search:
         cfg.hbm_budget_bytes = hbm_budget_bytes
         cfg.flags = 0
         cfg.reserved = 0
-        cfg.stream = ctypes.c_void_p(stream)
+        cfg.stream = ctypes.c_void_p(stream) if stream else None
         cfg.tune_cache_path = None
         self.device = device
         self.h = tno_search_create(cfg)

@@ -303,3 +303,90 @@ def test_ffi_full_size_sampled_parity():
         ora = _crop_oracle(R, sigma, times, t_ref, vel[j:j + 1], y0, y1, x0, x1, margin)
         parity.check_maps(snr[j:j + 1, y0:y1, x0:x1].cpu().numpy(),
                           flux[j:j + 1, y0:y1, x0:x1].cpu().numpy(), ora)
+
+
+# ------------------------------------------------------------------ serving: residency, streams
+
+def test_resident_stack_reuse_and_key_errors():
+    R, sigma, times, vel = _rand_problem(50, 10, 40, 150, 3)
+    ref, _ = run_gpu(R, sigma, times, vel, float(times[0]), top_k=8)
+    t = [_to(R), _to(sigma), _to(times), _to(vel)]
+    J, (T, H, W) = 3, R.shape
+    with tno.Search(0, own_streams=True) as h:
+        torch.cuda.synchronize()
+        o1, out1 = tno.alloc_outputs(J, H, W, 8)
+        req = tno.make_request(*t, t_ref=float(times[0]), top_k=8, stack_key=77)
+        h.wait(h.submit(req, out1))
+        o2, out2 = tno.alloc_outputs(J, H, W, 8)
+        req2 = tno.make_request(*t, t_ref=float(times[0]), top_k=8, stack_key=77)
+        req2.residuals = None       # served from the resident copy
+        h.wait(h.submit(req2, out2))
+        torch.cuda.synchronize()
+        for o in (o1, o2):
+            assert np.array_equal(o["snr"].cpu().numpy(), ref["snr"])
+        req3 = tno.make_request(*t, t_ref=float(times[0]), top_k=8, stack_key=78)
+        req3.residuals = None
+        rc, _ = tno.tno_search_submit(h.h, req3, out2)
+        assert rc == tno.TNO_E_INVAL
+        req4 = tno.make_request(t[0][:5], t[1], t[2][:5], t[3], top_k=8, stack_key=77)
+        rc, _ = tno.tno_search_submit(h.h, req4, out2)
+        assert rc == tno.TNO_E_INVAL      # same key, other shape
+
+
+def test_concurrent_requests_match_alone():
+    """Requests in flight together on the library's stream pool give the same
+    bits as each request alone."""
+    probs = [_rand_problem(60 + i, 6 + 3 * i, 40 + 7 * i, 130 + 20 * i, 2 + i) for i in range(4)]
+    alone = [run_gpu(R, s, t, v, float(t[0]), top_k=5)[0] for (R, s, t, v) in probs]
+    keep = []
+    with tno.Search(0, own_streams=True) as h:
+        tickets = []
+        for i, (R, s, t, v) in enumerate(probs):
+            tt = [_to(R), _to(s), _to(t), _to(v)]
+            o, out = tno.alloc_outputs(v.shape[0], R.shape[1], R.shape[2], 5)
+            torch.cuda.synchronize()
+            keep.append((tt, o, out))
+            tickets.append(h.submit(tno.make_request(*tt, t_ref=float(t[0]), top_k=5), out))
+        for tk in reversed(tickets):
+            h.wait(tk)
+    for (tt, o, out), a in zip(keep, alone):
+        assert np.array_equal(o["snr"].cpu().numpy(), a["snr"])
+        assert np.array_equal(o["best_traj"].cpu().numpy(), a["best_traj"])
+
+
+def test_lru_eviction_under_budget():
+    R, sigma, times, vel = _rand_problem(70, 8, 64, 128, 2)
+    t = [_to(R), _to(sigma), _to(times), _to(vel)]
+    o, out = tno.alloc_outputs(2, 64, 128, 4)
+    with tno.Search(0, own_streams=True) as h0:
+        torch.cuda.synchronize()
+        h0.wait(h0.submit(tno.make_request(*t, top_k=4, stack_key=1), out))
+    stack_bytes = R.nbytes + sigma.nbytes + 1024
+    with tno.Search(0, own_streams=True, hbm_budget_bytes=1) as tiny:
+        rc, _ = tno.tno_search_submit(tiny.h, tno.make_request(*t, top_k=4), out)
+        assert rc == tno.TNO_E_NOMEM
+    import ctypes
+    req = tno.make_request(*t, top_k=4)
+    # footprint of the arena alone (device pointers: estimate from a host twin)
+    hostreq = tno.tno_request()
+    ctypes.memmove(ctypes.byref(hostreq), ctypes.byref(req), ctypes.sizeof(req))
+    hostreq.flags = 0
+    keep = [R, sigma, times, vel]
+    hostreq.residuals = R.ctypes.data_as(ctypes.c_void_p)
+    hostreq.sigma = sigma.ctypes.data_as(ctypes.c_void_p)
+    hostreq.times = times.ctypes.data_as(ctypes.c_void_p)
+    hostreq.velocities = vel.ctypes.data_as(ctypes.c_void_p)
+    hostreq.stack_key = 5
+    fp = tno.tno_search_footprint(hostreq, tno.tno_outputs())
+    assert fp > 0
+    # room for one request's arena and two resident stacks, not three
+    with tno.Search(0, own_streams=True, hbm_budget_bytes=fp + stack_bytes) as h:
+        for key in (1, 2, 3):
+            h.wait(h.submit(tno.make_request(*t, top_k=4, stack_key=key), out))
+        r1 = tno.make_request(*t, top_k=4, stack_key=1)
+        r1.residuals = None
+        rc, _ = tno.tno_search_submit(h.h, r1, out)
+        assert rc == tno.TNO_E_INVAL            # key 1 was evicted (least recently used)
+        r3 = tno.make_request(*t, top_k=4, stack_key=3)
+        r3.residuals = None
+        h.wait(h.submit(r3, out))               # key 3 is still resident
