@@ -63,7 +63,9 @@ extern "C" {
 #define TNO_QTILE 64
 
 /* tno_config.flags */
-#define TNO_CFG_GRAPHS 1u           /* replay kernel sequences as HIP graphs */
+#define TNO_CFG_GRAPHS 1u           /* replay kernel sequences as HIP graphs (reserved) */
+#define TNO_CFG_AUTOTUNE 2u         /* time the search's tile shapes and trajectory blocks on the
+                                       first request of each shape class; keep the fastest */
 
 /* tno_request.flags */
 #define TNO_REQ_DEVICE_PTRS 1u      /* every input and output pointer is device memory */
@@ -82,7 +84,8 @@ typedef struct {
     uint32_t flags;              /* TNO_CFG_* */
     uint32_t reserved;           /* must be 0 */
     void *stream;                /* hipStream_t to run on, or NULL for an own stream */
-    const char *tune_cache_path; /* JSON tuning cache, or NULL */
+    const char *tune_cache_path; /* text tuning cache read at create and rewritten after each
+                                    tuning (one line per arch and shape class), or NULL */
 } tno_config;
 
 typedef struct {

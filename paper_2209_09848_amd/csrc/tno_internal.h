@@ -6,13 +6,22 @@
 
 namespace tno {
 
-// Search tile: 128 start-pixel columns (2 per lane) x SEARCH_TY rows (8 per
-// lane, one wave per 8 rows).
-constexpr int SEARCH_TX = 128;
+// Search tile shapes.  A lane owns CPL adjacent columns x SEARCH_RPL rows; a
+// wave spans 64*CPL columns; a block stacks NWAVE waves vertically.  Variant
+// 0 is the default; the others are autotuning candidates (stamp 5 only).
 constexpr int SEARCH_RPL = 8;
-constexpr int SEARCH_WAVES = 4;
-constexpr int SEARCH_TY = SEARCH_RPL * SEARCH_WAVES;
-constexpr int SEARCH_THREADS = 64 * SEARCH_WAVES;
+struct SearchVariant {
+    int nwave, cpl;
+    const char *name;
+};
+inline constexpr SearchVariant SEARCH_VARIANTS[] = {
+    {4, 2, "w4c2"}, {8, 2, "w8c2"}, {2, 2, "w2c2"}, {4, 1, "w4c1"}, {8, 1, "w8c1"}, {4, 4, "w4c4"},
+};
+constexpr int N_SEARCH_VARIANTS = 6;
+constexpr int SEARCH_MAX_TX = 256;
+constexpr int SEARCH_MAX_TY = 64;
+__host__ __device__ constexpr int search_tx(int v) { return 64 * SEARCH_VARIANTS[v].cpl; }
+__host__ __device__ constexpr int search_ty(int v) { return SEARCH_RPL * SEARCH_VARIANTS[v].nwave; }
 // Normaliser tile: 64 columns (1 per lane) x 32 rows (8 per lane, 4 waves).
 constexpr int LAMBDA_TX = 64;
 constexpr int LAMBDA_TY = 32;
@@ -50,9 +59,12 @@ struct SearchArgs {
     float *snr;              // [J][H][W]
     float *flux;             // [J][H][W]
     uint64_t *tile_keys;     // [J][ntiles]
+    const int32_t *perm;     // [J] search order of the trajectories (velocity-sorted)
     int H, W, T, J;
     int Hp, Wp4, Pt, Pl;
     int ntx, nty, n_items;
+    int tblock;              // trajectories per block of the work order
+    int nframes;             // frames to accumulate (T, or fewer for a tuning probe)
 };
 
 struct LambdaArgs {
@@ -78,7 +90,7 @@ hipError_t launch_trail(hipStream_t st, int J, int T, int S, int H, const int32_
                         const double *tab64, const TrailInfo *info, int2 *colmeta,
                         double *kvals, int32_t *err);
 hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a);
-hipError_t launch_search(hipStream_t st, int S, const SearchArgs &a);
+hipError_t launch_search(hipStream_t st, int S, int variant, const SearchArgs &a);
 hipError_t launch_trajmax(hipStream_t st, int J, int ntiles, int W, int HW,
                           const uint64_t *tile_keys, const float *snr, const float *flux,
                           void *traj_max_out);

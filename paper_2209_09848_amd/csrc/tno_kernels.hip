@@ -452,13 +452,13 @@ hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a)
 // pass of S taps per window row streamed into a vertical pass of S taps.  The
 // table entry (shift, PRF taps) is wave-uniform (scalar loads).  Frame
 // partials accumulate in FP32 over FRAME_CHUNK frames, then into FP64.
-template <int S>
-__global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a)
+template <int S, int NWAVE, int CPL>
+__global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
 {
     constexpr int h = S / 2;
-    constexpr int CPL = 2, RPL = SEARCH_RPL;
-    constexpr int NT = SEARCH_THREADS;
-    constexpr int TX = SEARCH_TX, TY = SEARCH_TY;
+    constexpr int RPL = SEARCH_RPL;
+    constexpr int NT = 64 * NWAVE;
+    constexpr int TX = 64 * CPL, TY = RPL * NWAVE;
     constexpr int WY = TY + S - 1;
     constexpr int NG = (TX + S - 1 + 3 + 3) / 4;
     constexpr int LS = NG * 4;
@@ -471,8 +471,15 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a)
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.n_items)
         return;
-    const int j = item % a.J;
-    const int tile = item / a.J;
+    // work order: blocks of `tblock` velocity-sorted trajectories; within a
+    // block the trajectory index runs fastest, then the tile
+    const int ntiles = a.ntx * a.nty;
+    const int per_blk = ntiles * a.tblock;
+    const int jb = item / per_blk;
+    const int rem = item - jb * per_blk;
+    const int bcur = min(a.tblock, a.J - jb * a.tblock);
+    const int tile = rem / bcur;
+    const int j = a.perm[jb * a.tblock + (rem - tile * bcur)];
     const int tyi = tile / a.ntx, txi = tile - tyi * a.ntx;
     const int ty0 = tyi * TY, tx0 = txi * TX;
     const int tid = threadIdx.x;
@@ -541,10 +548,10 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a)
     int d_cur = fetch(0, pre);
     store(0, pre);
     __syncthreads();
-    for (int k = 0; k < a.T; ++k) {
+    for (int k = 0; k < a.nframes; ++k) {
         const int buf = k & 1;
         int d_next = 0;
-        if (k + 1 < a.T)
+        if (k + 1 < a.nframes)
             d_next = fetch(k + 1, pre);
 
         const int32_t *e = tabj + (size_t)k * TS;
@@ -581,7 +588,7 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a)
                 }
             }
         }
-        if (k + 1 < a.T)
+        if (k + 1 < a.nframes)
             store(buf ^ 1, pre);
         __syncthreads();
         d_cur = d_next;
@@ -631,30 +638,48 @@ __global__ __launch_bounds__(SEARCH_THREADS) void k_search(SearchArgs a)
         uint64_t o = __shfl_xor(best, off, 64);
         best = o > best ? o : best;
     }
-    __shared__ uint64_t wbest[SEARCH_WAVES];
+    __shared__ uint64_t wbest[NWAVE];
     if (lane == 0)
         wbest[wv] = best;
     __syncthreads();
     if (tid == 0) {
         uint64_t m = wbest[0];
-        for (int w = 1; w < SEARCH_WAVES; ++w)
+        for (int w = 1; w < NWAVE; ++w)
             m = wbest[w] > m ? wbest[w] : m;
-        a.tile_keys[(size_t)j * (a.ntx * a.nty) + tile] = m;
+        a.tile_keys[(size_t)j * ntiles + tile] = m;
     }
 }
 
-hipError_t launch_search(hipStream_t st, int S, const SearchArgs &a)
+template <int S, int NWAVE, int CPL>
+static void launch_search_t(hipStream_t st, const SearchArgs &a)
 {
-    dim3 grid(xcd_grid(a.n_items)), block(SEARCH_THREADS);
+    hipLaunchKernelGGL((k_search<S, NWAVE, CPL>), dim3(xcd_grid(a.n_items)), dim3(64 * NWAVE), 0, st, a);
+}
+
+hipError_t launch_search(hipStream_t st, int S, int variant, const SearchArgs &a)
+{
+    if (S == 5) {
+        switch (variant) {
+        case 0: launch_search_t<5, 4, 2>(st, a); break;
+        case 1: launch_search_t<5, 8, 2>(st, a); break;
+        case 2: launch_search_t<5, 2, 2>(st, a); break;
+        case 3: launch_search_t<5, 4, 1>(st, a); break;
+        case 4: launch_search_t<5, 8, 1>(st, a); break;
+        case 5: launch_search_t<5, 4, 4>(st, a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (variant != 0)
+        return hipErrorInvalidValue;
     switch (S) {
-    case 1: hipLaunchKernelGGL(k_search<1>, grid, block, 0, st, a); break;
-    case 3: hipLaunchKernelGGL(k_search<3>, grid, block, 0, st, a); break;
-    case 5: hipLaunchKernelGGL(k_search<5>, grid, block, 0, st, a); break;
-    case 7: hipLaunchKernelGGL(k_search<7>, grid, block, 0, st, a); break;
-    case 9: hipLaunchKernelGGL(k_search<9>, grid, block, 0, st, a); break;
-    case 11: hipLaunchKernelGGL(k_search<11>, grid, block, 0, st, a); break;
-    case 13: hipLaunchKernelGGL(k_search<13>, grid, block, 0, st, a); break;
-    case 15: hipLaunchKernelGGL(k_search<15>, grid, block, 0, st, a); break;
+    case 1: launch_search_t<1, 4, 2>(st, a); break;
+    case 3: launch_search_t<3, 4, 2>(st, a); break;
+    case 7: launch_search_t<7, 4, 2>(st, a); break;
+    case 9: launch_search_t<9, 4, 2>(st, a); break;
+    case 11: launch_search_t<11, 4, 2>(st, a); break;
+    case 13: launch_search_t<13, 4, 2>(st, a); break;
+    case 15: launch_search_t<15, 4, 2>(st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -16,7 +16,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <numeric>
+#include <sstream>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -76,6 +79,9 @@ struct Plan {
     std::vector<tno::TrailInfo> trail;
     int64_t n_colmeta = 0, n_kvals = 0;
     int ntx = 0, nty = 0, ntiles = 0;
+    int variant = 0, tblock = 1;      // search tile shape and trajectory block of the work order
+    int ntiles_max = 0;               // tiles of the smallest shape (sizes the tile-key buffer)
+    std::vector<int32_t> perm;        // velocity-sorted search order
     int lntx = 0, lnty = 0;
     int64_t N = 0, n_chunks = 0;
     bool own_snr = true, own_flux = true;
@@ -85,7 +91,7 @@ struct Plan {
     size_t o_R = 0, o_scales = 0, o_sigma = 0, o_times = 0, o_vel = 0, o_Z = 0, o_iv32 = 0,
            o_iv64 = 0, o_tab32 = 0, o_tab64 = 0, o_trail = 0, o_colmeta = 0, o_kvals = 0,
            o_err = 0, o_lam = 0, o_snr = 0, o_flux = 0, o_tkeys = 0, o_tstate = 0, o_chunks = 0,
-           o_cand = 0, o_tmax = 0, o_topk = 0, o_best = 0, o_bestj = 0, bytes = 0;
+           o_cand = 0, o_tmax = 0, o_topk = 0, o_best = 0, o_bestj = 0, o_perm = 0, bytes = 0;
 };
 
 bool finite(double v) { return std::isfinite(v); }
@@ -134,11 +140,20 @@ Fail check_shape(const tno_request *r, const tno_outputs *o)
     const double jhw = (double)r->n_traj * r->height * r->width;
     if (jhw > 4.0e12)
         return fail(TNO_E_INVAL, "n_traj*height*width too large");
-    const double items = (double)r->n_traj * ((r->height + tno::SEARCH_TY - 1) / tno::SEARCH_TY) *
-                         ((r->width + tno::SEARCH_TX - 1) / tno::SEARCH_TX);
+    const double items = (double)r->n_traj * ((r->height + 15) / 16) * ((r->width + 63) / 64);
     if (items > 2.0e9)
         return fail(TNO_E_INVAL, "too many (tile, trajectory) work items");
     return fail(TNO_OK, "");
+}
+
+// Tile shape of search variant v and trajectory-block size of the work order.
+void set_search_shape(Plan &p, int v, int tblock)
+{
+    p.variant = v;
+    p.ntx = (p.W + tno::search_tx(v) - 1) / tno::search_tx(v);
+    p.nty = (p.H + tno::search_ty(v) - 1) / tno::search_ty(v);
+    p.ntiles = p.ntx * p.nty;
+    p.tblock = std::max(1, std::min(tblock, p.J));
 }
 
 // Build the plan from host copies of times and velocities.
@@ -215,14 +230,38 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     p.n_colmeta = std::max<int64_t>(coff, 1);
     p.n_kvals = std::max<int64_t>(voff, 1);
     p.Pt = std::min(PAD_CAP, std::max(0, -gymin) + h);
-    p.Pb = std::min(PAD_CAP, std::max(0, gymax) + h + tno::SEARCH_TY);
+    p.Pb = std::min(PAD_CAP, std::max(0, gymax) + h + tno::SEARCH_MAX_TY);
     p.Pl = (int)align_up((size_t)std::min(PAD_CAP, std::max(0, -gxmin) + h + 3), 4);
-    p.Pr = std::min(PAD_CAP, std::max(0, gxmax) + h + tno::SEARCH_TX + 4);
+    p.Pr = std::min(PAD_CAP, std::max(0, gxmax) + h + tno::SEARCH_MAX_TX + 4);
     p.Hp = H + p.Pt + p.Pb;
     p.Wp4 = (int)(align_up((size_t)W + p.Pl + p.Pr, 4) / 4);
-    p.ntx = (W + tno::SEARCH_TX - 1) / tno::SEARCH_TX;
-    p.nty = (H + tno::SEARCH_TY - 1) / tno::SEARCH_TY;
-    p.ntiles = p.ntx * p.nty;
+    set_search_shape(p, 0, p.J);
+    p.ntiles_max = ((W + 63) / 64) * ((H + 15) / 16);
+    // search order: Morton (Z-order) code of the quantised velocity, so that
+    // trajectories adjacent in the work order have nearby shifts and their
+    // windows share cache lines
+    {
+        double vxmin = INFINITY, vxmax = -INFINITY, vymin = INFINITY, vymax = -INFINITY;
+        for (int j = 0; j < p.J; ++j) {
+            vxmin = std::min(vxmin, vel[2 * j]);
+            vxmax = std::max(vxmax, vel[2 * j]);
+            vymin = std::min(vymin, vel[2 * j + 1]);
+            vymax = std::max(vymax, vel[2 * j + 1]);
+        }
+        std::vector<uint32_t> code(p.J);
+        for (int j = 0; j < p.J; ++j) {
+            auto q = [](double v, double lo, double hi) -> uint32_t {
+                return hi > lo ? (uint32_t)std::min(65535.0, std::floor((v - lo) / (hi - lo) * 65535.0)) : 0u;
+            };
+            uint32_t a = q(vel[2 * j], vxmin, vxmax), b = q(vel[2 * j + 1], vymin, vymax), c = 0;
+            for (int bit = 0; bit < 16; ++bit)
+                c |= (((a >> bit) & 1u) << (2 * bit)) | (((b >> bit) & 1u) << (2 * bit + 1));
+            code[j] = c;
+        }
+        p.perm.resize(p.J);
+        std::iota(p.perm.begin(), p.perm.end(), 0);
+        std::stable_sort(p.perm.begin(), p.perm.end(), [&](int32_t x, int32_t y) { return code[x] < code[y]; });
+    }
     p.lntx = (W + tno::LAMBDA_TX - 1) / tno::LAMBDA_TX;
     p.lnty = (H + tno::LAMBDA_TY - 1) / tno::LAMBDA_TY;
     if ((double)p.lntx * p.lnty * p.J > 2.0e9)
@@ -269,7 +308,8 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
         p.o_snr = take(J * HW * 4);
     if (p.own_flux)
         p.o_flux = take(J * HW * 4);
-    p.o_tkeys = take(J * p.ntiles * 8);
+    p.o_tkeys = take(J * p.ntiles_max * 8);
+    p.o_perm = take(J * 4);
     p.o_tstate = take(sizeof(tno::TopkState));
     p.o_chunks = take((size_t)p.n_chunks * 4);
     p.o_cand = take((size_t)TNO_MAX_TOPK * 16);
@@ -361,6 +401,44 @@ struct tno_search {
     std::map<uint64_t, Request *> live;
     std::map<uint64_t, Stack *> stacks;
     ArenaCache cache;
+    // tuning table: shape class -> (variant, trajectory block, probe updates/s)
+    struct Tuned {
+        int variant, tblock;
+        double rate;
+    };
+    bool autotune = false;
+    std::string arch;
+    std::string tune_path;
+    std::map<std::string, Tuned> tuned;
+
+    void load_tuning()
+    {
+        std::ifstream f(tune_path);
+        std::string line;
+        while (std::getline(f, line)) {
+            if (line.empty() || line[0] == '#')
+                continue;
+            std::istringstream ss(line);
+            std::string a, cls, vname;
+            int tb = 0;
+            double rate = 0;
+            if (!(ss >> a >> cls >> vname >> tb >> rate) || a != arch)
+                continue;
+            for (int v = 0; v < tno::N_SEARCH_VARIANTS; ++v)
+                if (vname == tno::SEARCH_VARIANTS[v].name)
+                    tuned[cls] = {v, tb, rate};
+        }
+    }
+    void save_tuning() const
+    {
+        if (tune_path.empty())
+            return;
+        std::ofstream f(tune_path, std::ios::trunc);
+        f << "# tno_search tuning cache: arch shape-class variant trajectory-block probe-updates/s\n";
+        for (auto &kv : tuned)
+            f << arch << " " << kv.first << " " << tno::SEARCH_VARIANTS[kv.second.variant].name << " "
+              << kv.second.tblock << " " << kv.second.rate << "\n";
+    }
 };
 
 namespace {
@@ -450,29 +528,60 @@ Inputs inputs_of(const Request *q, const tno_request *r)
     return in;
 }
 
-// Enqueue the whole search of one request on its stream.
-hipError_t enqueue(tno_search *hd, Request *q, const tno_request *r)
-{
-    (void)hd;
-    const Plan &p = q->plan;
-    hipStream_t st = q->stream;
-    void *A = q->arena;
-    const Inputs in = inputs_of(q, r);
-    float *snr = p.own_snr ? at<float>(A, p.o_snr) : q->out.snr;
-    float *flux = p.own_flux ? at<float>(A, p.o_flux) : q->out.flux;
-    const int HW = p.H * p.W;
-    hipError_t e;
 #define TRY(x)                  \
     do {                        \
         e = (x);                \
         if (e != hipSuccess)    \
             return e;           \
     } while (0)
+
+tno::SearchArgs search_args(const Request *q, float *snr, float *flux, int nframes)
+{
+    const Plan &p = q->plan;
+    void *A = q->arena;
+    tno::SearchArgs sa;
+    sa.Z4 = at<float4>(A, p.o_Z);
+    sa.tab32 = at<int32_t>(A, p.o_tab32);
+    sa.lam = at<double>(A, p.o_lam);
+    sa.snr = snr;
+    sa.flux = flux;
+    sa.tile_keys = at<uint64_t>(A, p.o_tkeys);
+    sa.perm = at<int32_t>(A, p.o_perm);
+    sa.H = p.H;
+    sa.W = p.W;
+    sa.T = p.T;
+    sa.J = p.J;
+    sa.Hp = p.Hp;
+    sa.Wp4 = p.Wp4;
+    sa.Pt = p.Pt;
+    sa.Pl = p.Pl;
+    sa.ntx = p.ntx;
+    sa.nty = p.nty;
+    sa.n_items = p.ntiles * p.J;
+    sa.tblock = p.tblock;
+    sa.nframes = nframes;
+    return sa;
+}
+
+float *snr_map(Request *q) { return q->plan.own_snr ? at<float>(q->arena, q->plan.o_snr) : q->out.snr; }
+float *flux_map(Request *q) { return q->plan.own_flux ? at<float>(q->arena, q->plan.o_flux) : q->out.flux; }
+
+// Enqueue everything before the numerator search: weighting, table, trail, Lam.
+hipError_t enqueue_front(Request *q, const tno_request *r)
+{
+    const Plan &p = q->plan;
+    hipStream_t st = q->stream;
+    void *A = q->arena;
+    const Inputs in = inputs_of(q, r);
+    const int HW = p.H * p.W;
+    hipError_t e;
     if (q->stack && q->stack->ready)
         TRY(hipStreamWaitEvent(st, q->stack->ready, 0));
     TRY(hipEventRecord(q->ev[0], st));
     TRY(tno::launch_zero(st, at<int32_t>(A, p.o_err), 1));
     TRY(hipMemcpyAsync(at<void>(A, p.o_trail), p.trail.data(), p.trail.size() * sizeof(tno::TrailInfo),
+                       hipMemcpyHostToDevice, st));
+    TRY(hipMemcpyAsync(at<void>(A, p.o_perm), p.perm.data(), p.perm.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice, st));
     TRY(tno::launch_ivar(st, HW, in.sigma, at<float>(A, p.o_iv32), at<double>(A, p.o_iv64),
                          at<int32_t>(A, p.o_err)));
@@ -499,25 +608,21 @@ hipError_t enqueue(tno_search *hd, Request *q, const tno_request *r)
     la.n_items = p.lntx * p.lnty * p.J;
     TRY(tno::launch_lambda(st, la));
     TRY(hipEventRecord(q->ev[3], st));
-    tno::SearchArgs sa;
-    sa.Z4 = at<float4>(A, p.o_Z);
-    sa.tab32 = at<int32_t>(A, p.o_tab32);
-    sa.lam = at<double>(A, p.o_lam);
-    sa.snr = snr;
-    sa.flux = flux;
-    sa.tile_keys = at<uint64_t>(A, p.o_tkeys);
-    sa.H = p.H;
-    sa.W = p.W;
-    sa.T = p.T;
-    sa.J = p.J;
-    sa.Hp = p.Hp;
-    sa.Wp4 = p.Wp4;
-    sa.Pt = p.Pt;
-    sa.Pl = p.Pl;
-    sa.ntx = p.ntx;
-    sa.nty = p.nty;
-    sa.n_items = p.ntiles * p.J;
-    TRY(tno::launch_search(st, p.S, sa));
+    return hipSuccess;
+}
+
+// Enqueue the numerator search, the reductions and the output copies.
+hipError_t enqueue_back(Request *q)
+{
+    const Plan &p = q->plan;
+    hipStream_t st = q->stream;
+    void *A = q->arena;
+    float *snr = snr_map(q);
+    float *flux = flux_map(q);
+    const int HW = p.H * p.W;
+    hipError_t e;
+    const tno::SearchArgs sa = search_args(q, snr, flux, p.T);
+    TRY(tno::launch_search(st, p.S, p.variant, sa));
     TRY(hipEventRecord(q->ev[4], st));
     TRY(tno::launch_trajmax(st, p.J, p.ntiles, p.W, HW, sa.tile_keys, snr, flux, at<void>(A, p.o_tmax)));
     TRY(tno::launch_best(st, p.J, HW, snr, at<float>(A, p.o_best), at<int32_t>(A, p.o_bestj)));
@@ -539,9 +644,76 @@ hipError_t enqueue(tno_search *hd, Request *q, const tno_request *r)
             TRY(hipMemcpyAsync(o.best_traj, at<void>(A, p.o_bestj), (size_t)HW * 4, hipMemcpyDeviceToDevice, st));
     }
     TRY(hipEventRecord(q->ev[5], st));
-#undef TRY
     return hipSuccess;
 }
+
+// Shape class of a request for the tuning table: stamp and the binary
+// orders of magnitude of H, W, J and T.
+std::string shape_class(const Plan &p)
+{
+    auto lg = [](int v) { int b = 0; while ((1 << b) < v) ++b; return b; };
+    char buf[64];
+    snprintf(buf, sizeof buf, "S%d_H%d_W%d_J%d_T%d", p.S, lg(p.H), lg(p.W), lg(p.J), lg(p.T));
+    return buf;
+}
+
+// Time every (tile shape, trajectory block) candidate on the first frames of
+// this request (its weighting, table and normaliser are already enqueued) and
+// keep the fastest for the request's shape class.  Synchronises the stream.
+hipError_t autotune(tno_search *h, Request *q)
+{
+    Plan &p = q->plan;
+    struct Cand {
+        int v, tb;
+        float ms;
+    };
+    std::vector<Cand> cands;
+    const int nv = p.S == 5 ? tno::N_SEARCH_VARIANTS : 1;
+    std::vector<int> tbs = {p.J};
+    for (int tb : {64, 16})
+        if (tb < p.J)
+            tbs.push_back(tb);
+    for (int v = 0; v < nv; ++v)
+        for (int tb : tbs)
+            cands.push_back({v, tb, 0.0f});
+    const int probe = std::min(p.T, 48);
+    std::vector<hipEvent_t> ev(2 * cands.size(), nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess)
+            e = hipEventCreate(&x);
+    for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
+        set_search_shape(p, cands[i].v, cands[i].tb);
+        const tno::SearchArgs sa = search_args(q, snr_map(q), flux_map(q), probe);
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {   // second run is timed
+            if (rep == 1)
+                e = hipEventRecord(ev[2 * i], q->stream);
+            if (e == hipSuccess)
+                e = tno::launch_search(q->stream, p.S, p.variant, sa);
+        }
+        if (e == hipSuccess)
+            e = hipEventRecord(ev[2 * i + 1], q->stream);
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(q->stream);
+    int best = 0;
+    for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
+        e = hipEventElapsedTime(&cands[i].ms, ev[2 * i], ev[2 * i + 1]);
+        if (cands[i].ms < cands[best].ms)
+            best = (int)i;
+    }
+    for (auto &x : ev)
+        if (x)
+            (void)hipEventDestroy(x);
+    if (e != hipSuccess)
+        return e;
+    set_search_shape(p, cands[best].v, cands[best].tb);
+    const double rate = (double)p.J * p.H * p.W * probe / (cands[best].ms * 1e-3);
+    h->tuned[shape_class(p)] = {cands[best].v, cands[best].tb, rate};
+    h->save_tuning();
+    return hipSuccess;
+}
+#undef TRY
 
 void release(tno_search *hd, Request *q)
 {
@@ -661,6 +833,18 @@ int tno_search_create(const tno_config *cfg, tno_search **out_handle)
         return hip_fail(e, "hipMemGetInfo", nullptr, 0);
     }
     h->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
+    h->autotune = (cfg->flags & TNO_CFG_AUTOTUNE) != 0;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, cfg->device) == hipSuccess) {
+        h->arch = prop.gcnArchName;
+        size_t colon = h->arch.find(':');
+        if (colon != std::string::npos)
+            h->arch.resize(colon);
+    }
+    if (cfg->tune_cache_path) {
+        h->tune_path = cfg->tune_cache_path;
+        h->load_tuning();
+    }
     *out_handle = h;
     return TNO_OK;
 }
@@ -842,7 +1026,16 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
                 return hip_fail(e, "copying inputs", nullptr, 0);
             }
     }
-    if ((e = enqueue(h, q, req)) != hipSuccess) {
+    bool tune_now = false;
+    {
+        auto it = h->tuned.find(shape_class(q->plan));
+        if (it != h->tuned.end() && (q->plan.S == 5 || it->second.variant == 0))
+            set_search_shape(q->plan, it->second.variant, it->second.tblock);
+        else
+            tune_now = h->autotune;
+    }
+    if ((e = enqueue_front(q, req)) != hipSuccess || (tune_now && (e = autotune(h, q)) != hipSuccess) ||
+        (e = enqueue_back(q)) != hipSuccess) {
         (void)hipStreamSynchronize(q->stream);
         release(h, q);
         return hip_fail(e, "enqueue", nullptr, 0);

@@ -28,6 +28,8 @@ TNO_E_INTERNAL = -7
 TNO_F32, TNO_BF16, TNO_F16, TNO_FP8_E4M3 = 0, 1, 2, 3
 TNO_PRF_GAUSS_SAMPLED, TNO_PRF_GAUSS_INTEGRATED = 0, 1
 TNO_CFG_GRAPHS = 1
+TNO_CFG_AUTOTUNE = 2
+SEARCH_VARIANTS = ("w4c2", "w8c2", "w2c2", "w4c1", "w8c1", "w4c4")
 TNO_REQ_DEVICE_PTRS = 1
 TNO_REQ_VALIDATE = 2
 TNO_MAX_TOPK = 1024
@@ -205,7 +207,8 @@ class Search:
     """One handle on torch's current stream of `device` (default cuda:0)."""
 
     def __init__(self, device: int = 0, max_inflight: int = 64, hbm_budget_bytes: int = 0,
-                 stream=None, own_streams: bool = False):
+                 stream=None, own_streams: bool = False, autotune: bool = False,
+                 tune_cache_path: str | None = None):
         """own_streams=True: the library runs requests on its own pool of streams
         (concurrent requests overlap; inputs must be complete before submit);
         otherwise every request runs on `stream` (default: torch's current)."""
@@ -218,10 +221,11 @@ class Search:
         cfg.device = device
         cfg.max_inflight = max_inflight
         cfg.hbm_budget_bytes = hbm_budget_bytes
-        cfg.flags = 0
+        cfg.flags = TNO_CFG_AUTOTUNE if autotune else 0
         cfg.reserved = 0
         cfg.stream = ctypes.c_void_p(stream) if stream else None
-        cfg.tune_cache_path = None
+        self._path = tune_cache_path.encode() if tune_cache_path else None
+        cfg.tune_cache_path = self._path
         self.device = device
         self.h = tno_search_create(cfg)
 
@@ -256,6 +260,12 @@ class Search:
             msg = res.message.decode(errors="replace") if res is not None else tno_search_last_error()
             raise TnoError(rc, msg)
         return res
+
+
+def shape_class(H, W, T, J, stamp=5) -> str:
+    """Tuning-table key the library uses for a request shape."""
+    lg = lambda v: max(0, (int(v) - 1).bit_length())
+    return "S%d_H%d_W%d_J%d_T%d" % (stamp, lg(H), lg(W), lg(J), lg(T))
 
 
 def alloc_outputs(J, H, W, k, device="cuda", maps=True):

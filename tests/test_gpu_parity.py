@@ -390,3 +390,46 @@ def test_lru_eviction_under_budget():
         r3 = tno.make_request(*t, top_k=4, stack_key=3)
         r3.residuals = None
         h.wait(h.submit(r3, out))               # key 3 is still resident
+
+
+# ------------------------------------------------------------------ batched form: tile shapes, autotuner
+
+def _arch():
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def test_every_tile_shape_and_block_gives_identical_bits(tmp_path):
+    """All search variants evaluate each output with the same operation order,
+    so forcing any (tile shape, trajectory block) through the tuning cache
+    must reproduce the default bits; one case also goes to the oracle."""
+    R, sigma, times, vel = _rand_problem(80, 11, 70, 300, 5)
+    T, H, W = R.shape
+    J = vel.shape[0]
+    ref, _ = run_gpu(R, sigma, times, vel, float(times[0]), top_k=20)
+    o = oracle.search(R, sigma, times, float(times[0]), vel)
+    parity.check_maps(ref["snr"], ref["flux"], o)
+    cls = tno.shape_class(H, W, T, J)
+    for name in tno.SEARCH_VARIANTS:
+        for tb in (J, 2):
+            path = tmp_path / ("tune_%s_%d.txt" % (name, tb))
+            path.write_text("%s %s %s %d 1.0\n" % (_arch(), cls, name, tb))
+            print("variant", name, "tblock", tb, flush=True)
+            with tno.Search(0, tune_cache_path=str(path)) as h:
+                g, res = run_gpu(R, sigma, times, vel, float(times[0]), top_k=20, handle=h)
+            assert np.array_equal(g["snr"], ref["snr"]) and np.array_equal(g["flux"], ref["flux"])
+            assert g["topk"] == ref["topk"]
+            assert np.array_equal(g["best_traj"], ref["best_traj"])
+
+
+def test_autotune_writes_cache_and_keeps_results(tmp_path):
+    R, sigma, times, vel = _rand_problem(81, 60, 100, 260, 20)
+    ref, _ = run_gpu(R, sigma, times, vel, float(times[0]), top_k=10)
+    path = tmp_path / "tune.txt"
+    with tno.Search(0, autotune=True, tune_cache_path=str(path)) as h:
+        g, res = run_gpu(R, sigma, times, vel, float(times[0]), top_k=10, handle=h)
+    assert np.array_equal(g["snr"], ref["snr"])
+    lines = [l for l in path.read_text().splitlines() if not l.startswith("#")]
+    assert len(lines) == 1
+    arch, cls, name, tb, rate = lines[0].split()
+    assert arch == _arch() and cls == tno.shape_class(60, 100, 260, 20)
+    assert name in tno.SEARCH_VARIANTS and 1 <= int(tb) <= 20 and float(rate) > 0
