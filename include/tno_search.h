@@ -98,18 +98,23 @@ typedef struct {
     int32_t height, width;       /* H, W > 0 */
     int32_t n_frames;            /* T > 0 */
     int32_t dtype;               /* TNO_F32 / TNO_BF16 / TNO_F16 / TNO_FP8_E4M3 */
-    const void *residuals;       /* [T][H][W] of dtype (float, or uint16/uint8 codes) */
+    const void *residuals;       /* [T][H][W] of dtype (float, or uint16/uint8 codes); NULL to
+                                    search the stack resident under stack_key */
     const float *tile_scales;    /* [T][ceil(H/64)][ceil(W/64)]: value = code * scale;
-                                    required unless dtype == TNO_F32 */
-    const float *sigma;          /* [H][W] per-pixel noise sigma */
+                                    required with residuals unless dtype == TNO_F32 */
+    const float *sigma;          /* [H][W] per-pixel noise sigma; required with residuals
+                                    (a resident stack keeps its own) */
     const double *times;         /* [T] frame times, any finite values (gaps allowed) */
     double t_ref;                /* reference time of the start pixel; NaN: times[0] */
     tno_prf prf;
     int32_t n_traj;              /* J >= 1 */
     int32_t top_k;               /* candidates wanted, 0..TNO_MAX_TOPK */
     const double *velocities;    /* [J][2] = (vx, vy) in pixels per unit of `times` */
-    uint64_t stack_key;          /* 0, or a key under which the prepared stack stays
-                                    resident for later requests on the same data */
+    uint64_t stack_key;          /* 0, or a key: with residuals, the library keeps a device copy
+                                    of residuals, scales and sigma under the key (evicted least
+                                    recently used when the budget needs room); with NULL
+                                    residuals the resident copy is searched (TNO_E_INVAL if the
+                                    key is not resident or has another shape or dtype) */
     uint32_t flags;              /* TNO_REQ_* */
     uint32_t reserved;           /* must be 0 */
 } tno_request;

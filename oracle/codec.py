@@ -45,31 +45,24 @@ _POS_CODES = np.array([c for c in range(0x7F)], dtype=np.int64)  # 0x00..0x7E fi
 _POS_VALS = _E4M3[_POS_CODES]
 
 
-def _e4m3_encode_flat(x: np.ndarray) -> np.ndarray:
+def e4m3_encode(x) -> np.ndarray:
+    """Round-to-nearest-even, saturating encode of finite values to E4M3fn codes.
+
+    The non-negative finite codes 0x00..0x7E decode to increasing values, so
+    the two codes bracketing |x| are found by bisection; the nearer wins, and
+    an exact tie goes to the code with an even mantissa (lowest bit 0)."""
+    x = np.asarray(x, dtype=np.float64)
     a = np.minimum(np.abs(x), 448.0)
-    # exhaustive nearest search over the 127 non-negative finite codes
-    d = np.abs(a[:, None] - _POS_VALS[None, :])
-    best = d.min(axis=-1, keepdims=True)
-    cand = d == best
-    # ties: prefer the code with an even mantissa (lowest bit 0)
-    even = (_POS_CODES & 1) == 0
-    pick_even = cand & even[None, :]
-    has_even = pick_even.any(axis=-1, keepdims=True)
-    cand = np.where(has_even, pick_even, cand)
-    code = _POS_CODES[np.argmax(cand, axis=-1)]
+    hi = np.searchsorted(_POS_VALS, a, side="left")          # _POS_VALS[hi-1] < a <= _POS_VALS[hi]
+    hi = np.minimum(hi, _POS_VALS.size - 1)
+    lo = np.maximum(hi - 1, 0)
+    dlo = a - _POS_VALS[lo]
+    dhi = _POS_VALS[hi] - a
+    pick_hi = (dhi < dlo) | ((dhi == dlo) & ((_POS_CODES[hi] & 1) == 0))
+    code = np.where(pick_hi, _POS_CODES[hi], _POS_CODES[lo])
+    code = np.where(a == _POS_VALS[hi], _POS_CODES[hi], code)
     sign = (np.signbit(x) & (code != 0)).astype(np.int64) << 7
     return (code | sign).astype(np.uint8)
-
-
-def e4m3_encode(x) -> np.ndarray:
-    """Round-to-nearest-even, saturating encode of finite values to E4M3fn codes."""
-    x = np.asarray(x, dtype=np.float64)
-    flat = x.reshape(-1)
-    out = np.empty(flat.shape, np.uint8)
-    step = 1 << 15
-    for s in range(0, flat.size, step):
-        out[s:s + step] = _e4m3_encode_flat(flat[s:s + step])
-    return out.reshape(x.shape)
 
 
 def e4m3_decode(c) -> np.ndarray:
@@ -108,23 +101,32 @@ def pow2_scale(amax: float, E: int) -> float:
     return float(np.ldexp(1.0, int(c) - E))
 
 
+def pow2_scales(amax: np.ndarray, E: int) -> np.ndarray:
+    """pow2_scale applied elementwise."""
+    m, e = np.frexp(amax.astype(np.float64))
+    c = np.where(m == 0.5, e - 1, e)
+    return np.where(amax == 0.0, 1.0, np.ldexp(1.0, c - E)).astype(np.float32)
+
+
 def quantize(R, dtype: str):
     """Quantize a [T][H][W] float32 stack.  Returns (codes, scales) with
-    scales [T][ceil(H/64)][ceil(W/64)] float32."""
+    scales [T][ceil(H/64)][ceil(W/64)] float32.  Frame by frame: the frame is
+    zero-padded to whole tiles (padding does not change a tile's amax), each
+    tile's scale comes from its amax, and every value is encoded as R/s."""
     R = np.asarray(R, dtype=np.float32)
     T, H, W = R.shape
     ty, tx = -(-H // TILE), -(-W // TILE)
     E = E_BITS[dtype]
     scales = np.zeros((T, ty, tx), np.float32)
     codes = np.zeros(R.shape, np.uint8 if dtype == "fp8_e4m3" else np.uint16)
+    pad = np.zeros((ty * TILE, tx * TILE), np.float32)
     for k in range(T):
-        for a in range(ty):
-            for b in range(tx):
-                blk = R[k, a * TILE:(a + 1) * TILE, b * TILE:(b + 1) * TILE]
-                s = pow2_scale(float(np.max(np.abs(blk))), E)
-                scales[k, a, b] = s
-                codes[k, a * TILE:(a + 1) * TILE, b * TILE:(b + 1) * TILE] = \
-                    ENCODE[dtype](blk / np.float32(s))
+        pad[:H, :W] = R[k]
+        amax = np.abs(pad).reshape(ty, TILE, tx, TILE).max(axis=(1, 3))
+        s = pow2_scales(amax, E)
+        scales[k] = s
+        sfull = np.repeat(np.repeat(s, TILE, axis=0), TILE, axis=1)[:H, :W]
+        codes[k] = ENCODE[dtype](R[k] / sfull)
     return codes, scales
 
 

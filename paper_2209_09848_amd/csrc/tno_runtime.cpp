@@ -115,12 +115,15 @@ Fail check_shape(const tno_request *r, const tno_outputs *o)
         return fail(TNO_E_INVAL, "n_traj must be >= 1");
     if (r->dtype < TNO_F32 || r->dtype > TNO_FP8_E4M3)
         return fail(TNO_E_INVAL, "unknown dtype %d", r->dtype);
-    if (r->dtype != TNO_F32 && !r->tile_scales)
-        return fail(TNO_E_INVAL, "tile_scales required for reduced-precision residuals");
     if (!r->residuals && r->stack_key == 0)
         return fail(TNO_E_INVAL, "residuals is NULL and no stack_key given");
-    if (!r->sigma || !r->times || !r->velocities)
-        return fail(TNO_E_INVAL, "sigma, times and velocities must be non-NULL");
+    // residuals, scales and sigma of a resident stack come from its copy
+    if (r->residuals && r->dtype != TNO_F32 && !r->tile_scales)
+        return fail(TNO_E_INVAL, "tile_scales required for reduced-precision residuals");
+    if (r->residuals && !r->sigma)
+        return fail(TNO_E_INVAL, "sigma must be non-NULL");
+    if (!r->times || !r->velocities)
+        return fail(TNO_E_INVAL, "times and velocities must be non-NULL");
     if (r->prf.kind != TNO_PRF_GAUSS_SAMPLED && r->prf.kind != TNO_PRF_GAUSS_INTEGRATED)
         return fail(TNO_E_INVAL, "unknown PRF kind %d", r->prf.kind);
     if (r->prf.stamp < 1 || r->prf.stamp > TNO_MAX_STAMP || (r->prf.stamp % 2) == 0)

@@ -1,0 +1,240 @@
+"""Serving driver: a Poisson stream of uneven search requests against one handle.
+
+Requests differ in cutout size (256..2048 px, multiples of 256), frame count
+(200..1000) and trajectory set (16..256 drawn from the uneven-shell bank).
+Residual stacks live on the device under stack keys drawn from a pool (about
+half the requests reuse a resident stack); the library's stream pool runs
+admitted requests concurrently and its budget admission refuses work
+(TNO_E_BUSY) until memory or slots free up, in which case the request waits
+in this driver's FIFO.  Latency = completion seen by poll - arrival time.
+
+The driver marshals requests only; the search runs in libtno_search.so.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import math
+import sys
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import synth, tno
+
+
+@dataclass
+class Spec:
+    key: int
+    side: int
+    frames: int
+    traj_idx: np.ndarray     # rows of the shell bank
+    arrival: float = 0.0
+
+
+def draw_stack_shapes(n_keys: int, seed: int, sides=None, frames=(200, 1000)):
+    g = synth.rng(5, 3, seed)
+    sides = sides or [256 * i for i in range(1, 9)]
+    return {k + 1: (int(g.choice(sides)), int(g.integers(frames[0], frames[1] + 1)))
+            for k in range(n_keys)}
+
+
+def draw_requests(n: int, shapes: dict, bank_size: int, seed: int, jrange=(16, 256),
+                  reuse: float = 0.5):
+    """n request specs; a request reuses the previous key with probability
+    `reuse`, else draws a key from the pool."""
+    g = synth.rng(5, 3, 1000 + seed)
+    keys = sorted(shapes)
+    out = []
+    prev = None
+    for _ in range(n):
+        if prev is not None and g.random() < reuse:
+            key = prev
+        else:
+            key = int(g.choice(keys))
+        prev = key
+        side, frames = shapes[key]
+        J = int(g.integers(jrange[0], jrange[1] + 1))
+        idx = np.sort(g.choice(bank_size, size=J, replace=False))
+        out.append(Spec(key, side, frames, idx))
+    return out
+
+
+def poisson_arrivals(specs, rate: float, seed: int):
+    g = synth.rng(5, 3, 2000 + seed)
+    t = 0.0
+    for s in specs:
+        t += float(g.exponential(1.0 / rate))
+        s.arrival = t
+    return specs
+
+
+class StackPool:
+    """Device-side residual stacks by key, drawn on first use and handed to the
+    library once (it keeps its own resident copy); later requests on the key
+    pass no residuals."""
+
+    def __init__(self, shapes, dtype, device):
+        import torch
+        self.torch = torch
+        self.shapes = shapes
+        self.dtype = dtype
+        self.device = device
+        self.sigma = {}
+        self.times = {}
+
+    def inputs(self, key):
+        torch = self.torch
+        side, frames = self.shapes[key]
+        if key not in self.sigma:
+            g = synth.rng(5, 0, key)
+            self.sigma[key] = torch.from_numpy(synth.sigma_lognormal(g, side, side)).to(self.device)
+            self.times[key] = torch.from_numpy(synth.times_with_gap(frames, frames // 2)).to(self.device)
+        return self.sigma[key], self.times[key]
+
+    def residuals(self, key):
+        """Freshly drawn stack (and scales) for the first submission of `key`."""
+        torch = self.torch
+        side, frames = self.shapes[key]
+        sig, _ = self.inputs(key)
+        gen = torch.Generator(device=self.device)
+        gen.manual_seed(key)
+        R = torch.randn((frames, side, side), generator=gen, device=self.device) * sig
+        if self.dtype == "f32":
+            return R, None
+        codes = torch.empty((frames, side, side), device=self.device,
+                            dtype=torch.uint8 if self.dtype == "fp8_e4m3" else torch.int16)
+        scales = torch.empty((frames, (side + 63) // 64, (side + 63) // 64), device=self.device)
+        rc = tno.tno_quantize(frames, side, side, tno.DTYPE_CODE[self.dtype], R.data_ptr(),
+                              codes.data_ptr(), scales.data_ptr(), None)
+        if rc != 0:
+            raise tno.TnoError(rc, tno.tno_search_last_error())
+        torch.cuda.synchronize()
+        del R
+        return codes, scales
+
+
+def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=16,
+               max_inflight=8, log=None):
+    """Serve `specs` in arrival order.  Returns per-request records."""
+    import torch
+    pool = StackPool({s.key: (s.side, s.frames) for s in specs}, dtype, device)
+    vel_all = torch.from_numpy(bank).to(device)
+    known = set()
+    staged = {}
+    recs = []
+    queue = collections.deque()
+    pending = collections.deque(sorted(specs, key=lambda s: s.arrival))
+    inflight = {}
+    h = tno.Search(0, own_streams=True, max_inflight=max_inflight,
+                   hbm_budget_bytes=int(budget_gb * 1e9))
+    t0 = time.perf_counter()
+    try:
+        while pending or queue or inflight:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+            while queue:
+                s = queue[0]
+                sig, times = pool.inputs(s.key)
+                vel = vel_all[torch.from_numpy(s.traj_idx).to(device)].contiguous()
+                R = scales = None
+                if s.key not in known:
+                    if staged.get(s.key) is None:
+                        staged[s.key] = pool.residuals(s.key)
+                        torch.cuda.synchronize()
+                    R, scales = staged[s.key]
+                req = tno.make_request(R, sig if R is not None else None, times, vel, dtype=dtype,
+                                       scales=scales, top_k=top_k, stack_key=s.key,
+                                       shape=(s.frames, s.side, s.side))
+                o, out = tno.alloc_outputs(vel.shape[0], s.side, s.side, top_k, device=device,
+                                           maps=False)
+                rc, ticket = tno.tno_search_submit(h.h, req, out)
+                if rc == tno.TNO_E_BUSY:
+                    break
+                if rc == tno.TNO_E_INVAL and R is None:
+                    known.discard(s.key)   # evicted by the library: hand the stack over again
+                    continue
+                if rc != tno.TNO_OK:
+                    raise tno.TnoError(rc, tno.tno_search_last_error())
+                known.add(s.key)
+                staged.pop(s.key, None)
+                inflight[ticket] = (s, o, vel, R, scales)
+                queue.popleft()
+            done = []
+            for ticket in list(inflight):
+                rc, res = tno.tno_search_poll(h.h, ticket, 0)
+                if rc == tno.TNO_PENDING:
+                    continue
+                if rc != tno.TNO_OK:
+                    raise tno.TnoError(rc, res.message.decode(errors="replace"))
+                s = inflight[ticket][0]
+                t_done = time.perf_counter() - t0
+                recs.append({"key": s.key, "side": s.side, "frames": s.frames,
+                             "traj": int(len(s.traj_idx)), "arrival": s.arrival, "done": t_done,
+                             "latency_ms": (t_done - s.arrival) * 1e3, "device_ms": res.device_ms,
+                             "updates": int(res.updates),
+                             "topk": tno.decode_candidates(inflight[ticket][1]["topk"], res.n_topk)})
+                done.append(ticket)
+                if log:
+                    log("done key %d %dx%dx%d J=%d latency %.1f ms" %
+                        (s.key, s.side, s.side, s.frames, len(s.traj_idx), recs[-1]["latency_ms"]))
+            for t in done:
+                del inflight[t]
+            if not done:
+                time.sleep(0.0005)
+    finally:
+        h.close()
+    return recs
+
+
+def summarize(recs, warm: int = 0):
+    r = sorted(recs, key=lambda x: x["arrival"])[warm:]
+    lat = np.array([x["latency_ms"] for x in r])
+    span = max(x["done"] for x in r) - min(x["arrival"] for x in r)
+    return {"requests": len(r), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "updates_per_s": float(sum(x["updates"] for x in r) / span)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--requests", type=int, default=150)
+    ap.add_argument("--warm", type=int, default=20)
+    ap.add_argument("--keys", type=int, default=12)
+    ap.add_argument("--load", type=float, default=0.7, help="arrival rate / back-to-back capacity")
+    ap.add_argument("--budget-gb", type=float, default=0.0)
+    ap.add_argument("--max-side", type=int, default=2048)
+    ap.add_argument("--dtypes", default="f32,bf16")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args(argv)
+
+    def log(m):
+        print("[serve] " + m, file=sys.stderr, flush=True)
+
+    bank, _ = synth.grid_shells()
+    sides = [s for s in range(256, args.max_side + 1, 256)]
+    shapes = draw_stack_shapes(args.keys, args.seed, sides=sides)
+    specs = draw_requests(args.requests + args.warm, shapes, bank.shape[0], args.seed)
+    # capacity: back-to-back service rate of the FP32 form on a sample of the mix
+    cal = [Spec(s.key, s.side, s.frames, s.traj_idx, 0.0) for s in specs[:12]]
+    log("calibrating back-to-back capacity on %d requests" % len(cal))
+    crec = run_stream(cal, bank, dtype="f32", budget_gb=args.budget_gb, max_inflight=1)
+    mean_s = float(np.mean([x["device_ms"] for x in crec])) * 1e-3
+    rate = args.load / mean_s
+    log("mean device time %.1f ms -> arrival rate %.2f req/s" % (mean_s * 1e3, rate))
+    out = {"load": args.load, "arrival_rate_per_s": rate, "forms": {}}
+    for dt in args.dtypes.split(","):
+        sp = poisson_arrivals([Spec(s.key, s.side, s.frames, s.traj_idx) for s in specs], rate,
+                              args.seed)
+        log("serving %d requests, dtype %s" % (len(sp), dt))
+        recs = run_stream(sp, bank, dtype=dt, budget_gb=args.budget_gb, log=None)
+        out["forms"][dt] = summarize(recs, args.warm)
+        log("%s: %s" % (dt, json.dumps(out["forms"][dt])))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

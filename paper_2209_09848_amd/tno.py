@@ -182,9 +182,10 @@ def _ptr(t):
 
 def make_request(R, sigma, times, vel, *, t_ref=float("nan"), dtype="f32", scales=None,
                  sigma_px=0.7, stamp=5, prf_kind=TNO_PRF_GAUSS_SAMPLED, top_k=10,
-                 stack_key=0, flags=TNO_REQ_DEVICE_PTRS) -> tno_request:
-    """A request over torch tensors on the GPU (device pointers)."""
-    T, H, W = (int(s) for s in R.shape)
+                 stack_key=0, flags=TNO_REQ_DEVICE_PTRS, shape=None) -> tno_request:
+    """A request over torch tensors on the GPU (device pointers).  R may be
+    None (search the stack resident under stack_key) with shape=(T, H, W)."""
+    T, H, W = (int(s) for s in (R.shape if R is not None else shape))
     req = tno_request()
     req.height, req.width, req.n_frames = H, W, T
     req.dtype = DTYPE_CODE[dtype] if isinstance(dtype, str) else int(dtype)

@@ -377,7 +377,7 @@ def test_lru_eviction_under_budget():
     hostreq.times = times.ctypes.data_as(ctypes.c_void_p)
     hostreq.velocities = vel.ctypes.data_as(ctypes.c_void_p)
     hostreq.stack_key = 5
-    fp = tno.tno_search_footprint(hostreq, tno.tno_outputs())
+    fp = tno.tno_search_footprint(hostreq, out)
     assert fp > 0
     # room for one request's arena and two resident stacks, not three
     with tno.Search(0, own_streams=True, hbm_budget_bytes=fp + stack_bytes) as h:
@@ -431,5 +431,5 @@ def test_autotune_writes_cache_and_keeps_results(tmp_path):
     lines = [l for l in path.read_text().splitlines() if not l.startswith("#")]
     assert len(lines) == 1
     arch, cls, name, tb, rate = lines[0].split()
-    assert arch == _arch() and cls == tno.shape_class(60, 100, 260, 20)
+    assert arch == _arch() and cls == tno.shape_class(100, 260, 60, 20)
     assert name in tno.SEARCH_VARIANTS and 1 <= int(tb) <= 20 and float(rate) > 0

@@ -1,0 +1,126 @@
+"""Precision form at the FFI size: reduced-precision residual storage with
+per-64x64-tile power-of-two scales and FP32 accumulation.
+
+For each storage type the test reports (one JSON line each, printed):
+* codes and scales bit-exact against the oracle codec on tile-aligned crops;
+* arithmetic parity: GPU SNR vs the FP64 oracle run on the dequantized values;
+* quantization error: GPU SNR vs the FP64 oracle on the original FP32 values;
+* the injected-source detection set at 5 and 3 sigma vs the FP32 search.
+"""
+import json
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import codec, oracle
+from paper_2209_09848_amd import synth, tno
+from tests import parity
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+DEV = "cuda:0"
+H = W = 2048
+T = 1000
+# stated bounds on the SNR error against FP64 on the original values (rms over
+# the sampled hypotheses); derived from the codes' relative rounding error
+# (bf16 2^-9, f16 2^-12, e4m3 2^-5 at most) times sqrt(sum (W Z)^2)/sqrt(Lam) ~ 1
+RMS_BOUND = {"bf16": 3e-3, "f16": 4e-4, "fp8_e4m3": 5e-2}
+
+
+def _to(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _search(Rt, sig, times, t_ref, vel, dtype, scales=None):
+    o, res = tno.search_tensors(Rt, _to(sig), _to(times), _to(vel), t_ref=t_ref, top_k=100,
+                                dtype=dtype, scales=scales)
+    torch.cuda.synchronize()
+    assert res.status == 0
+    return o
+
+
+def _recovered(snr, src):
+    """Per source: max SNR over its true trajectory within +-1 px of the rounded start."""
+    out = []
+    for s in src:
+        yr, xr = int(math.floor(s.y + 0.5)), int(math.floor(s.x + 0.5))
+        out.append(float(snr[s.traj, max(0, yr - 1):yr + 2, max(0, xr - 1):xr + 2].max()))
+    return np.array(out)
+
+
+def test_precision_form_report():
+    R, sigma, times, t_ref, vel, src = synth.make_ffi_like_torch(H, W, T, DEV, amp=(0.02, 0.3),
+                                                                 config_id=3)
+    f32 = _search(R, sigma, times, t_ref, vel, "f32")
+    snr32 = f32["snr"]
+    rec32 = _recovered(snr32, src)
+    del f32
+    # sampled hypotheses: the 50 slower trajectories (trails <= ~40 px, so the
+    # crops stay small enough for the oracle's codec) at two 16x16 patches;
+    # crops aligned to quantization tiles and containing every stamp they touch
+    js = np.arange(50)
+    vel_s = vel[js]
+    margin = int(math.ceil(np.abs(vel_s).max() * (times.max() - t_ref))) + 4
+    regions = [(1024, 1040, 1024, 1040), (64, 80, 1600, 1616)]
+    crops = []
+    for (y0, y1, x0, x1) in regions:
+        cy0, cy1 = max(0, (y0 - margin) // 64 * 64), min(H, -(-(y1 + margin) // 64) * 64)
+        cx0, cx1 = max(0, (x0 - margin) // 64 * 64), min(W, -(-(x1 + margin) // 64) * 64)
+        Rc = R[:, cy0:cy1, cx0:cx1].cpu().numpy()
+        reg = (y0 - cy0, y1 - cy0, x0 - cx0, x1 - cx0)
+        ora = oracle.search(Rc, sigma[cy0:cy1, cx0:cx1], times, t_ref, vel_s, region=reg)
+        crops.append(((cy0, cy1, cx0, cx1), Rc, reg, ora))
+        g = snr32[js, y0:y1, x0:x1].cpu().numpy()
+        e = np.abs(g - ora["snr"]) / np.maximum(1.0, np.abs(ora["snr"]))
+        assert e.max() <= 1e-5
+    report = {}
+    for dtype in ("bf16", "f16", "fp8_e4m3"):
+        print("precision form", dtype, flush=True)
+        codes = torch.empty((T, H, W), device=DEV,
+                            dtype=torch.uint8 if dtype == "fp8_e4m3" else torch.int16)
+        scales = torch.empty((T, H // 64, W // 64), device=DEV)
+        assert tno.tno_quantize(T, H, W, tno.DTYPE_CODE[dtype], R.data_ptr(), codes.data_ptr(),
+                                scales.data_ptr(), None) == 0
+        torch.cuda.synchronize()
+        o = _search(codes, sigma, times, t_ref, vel, dtype, scales=scales)
+        snr = o["snr"]
+        err_orig, err_arith = [], []
+        for (cy0, cy1, cx0, cx1), Rc, reg, ora in crops:
+            npdt = np.uint8 if dtype == "fp8_e4m3" else np.uint16
+            cg = codes[:, cy0:cy1, cx0:cx1].cpu().numpy().view(npdt)
+            sg = scales[:, cy0 // 64:cy1 // 64, cx0 // 64:cx1 // 64].cpu().numpy()
+            co, so = codec.quantize(Rc, dtype)
+            assert np.array_equal(cg, co) and np.array_equal(sg, so)
+            deq = codec.dequantize(co, so, dtype)
+            od = oracle.search(deq, sigma[cy0:cy1, cx0:cx1], times, t_ref, vel_s, region=reg)
+            y0, y1, x0, x1 = reg[0] + cy0, reg[1] + cy0, reg[2] + cx0, reg[3] + cx0
+            g = snr[js, y0:y1, x0:x1].cpu().numpy().astype(np.float64)
+            err_arith.append(np.abs(g - od["snr"]) / np.maximum(1.0, np.abs(od["snr"])))
+            err_orig.append(np.abs(g - ora["snr"]))
+        ea = np.concatenate([e.ravel() for e in err_arith])
+        eo = np.concatenate([e.ravel() for e in err_orig])
+        rec = _recovered(snr, src)
+        d5 = int(np.sum((rec >= 5) != (rec32 >= 5)))
+        d3 = int(np.sum((rec >= 3) != (rec32 >= 3)))
+        near = [float(r) for r, r32 in zip(rec, rec32) if (r >= 5) != (r32 >= 5) or (r >= 3) != (r32 >= 3)]
+        report[dtype] = {"arith_max_rel": float(ea.max()), "orig_max_abs": float(eo.max()),
+                         "orig_rms": float(np.sqrt(np.mean(eo ** 2))),
+                         "recovered_5sigma": int(np.sum(rec >= 5)), "recovered_3sigma": int(np.sum(rec >= 3)),
+                         "fp32_5sigma": int(np.sum(rec32 >= 5)), "fp32_3sigma": int(np.sum(rec32 >= 3)),
+                         "set_changes_5sigma": d5, "set_changes_3sigma": d3,
+                         "changed_source_snrs": near,
+                         "source_snr_max_abs_change": float(np.max(np.abs(rec - rec32)))}
+        print("PRECISION " + json.dumps({dtype: report[dtype]}), flush=True)
+        assert ea.max() <= 1e-5
+        assert report[dtype]["orig_rms"] <= RMS_BOUND[dtype]
+        # a detection can only flip for a source whose SNR sits within the
+        # quantization error of the threshold
+        tol = 8 * RMS_BOUND[dtype]
+        for r, r32 in zip(rec, rec32):
+            for th in (3.0, 5.0):
+                if (r >= th) != (r32 >= th):
+                    assert abs(r32 - th) <= tol, (dtype, th, r32, r)
+        del codes, scales, o, snr
+        torch.cuda.empty_cache()
