@@ -15,6 +15,7 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 #include <limits.h>
+#include <type_traits>
 
 #include "tno_internal.h"
 #include "../../include/tno_search.h"
@@ -22,6 +23,8 @@
 namespace tno {
 
 // ------------------------------------------------------------------ helpers
+
+typedef __attribute__((address_space(4))) int32_t cint32_t;   // constant address space
 
 __device__ __forceinline__ uint32_t ordered_key(float f)
 {
@@ -497,12 +500,14 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
     // only the last slot can fall past the window
     const bool last_ok = tid + NT * (NLD - 1) < NWIN;
 
-    const int32_t *tabj = a.tab32 + (size_t)j * a.T * TS;
+    // the table is read-only for the whole launch: read it through the
+    // constant address space so its wave-uniform entries stay scalar loads
+    const cint32_t *tabj = (const cint32_t *)(a.tab32) + (size_t)j * a.T * TS;
     const size_t frame4 = (size_t)a.Hp * a.Wp4;
 
     // Fetch the window of frame k into registers; returns its sub-float4 offset.
     auto fetch = [&](int k, float4 (&pre)[NLD]) -> int {
-        const int32_t *e = tabj + (size_t)k * TS;
+        const cint32_t *e = tabj + (size_t)k * TS;
         const int oy = ty0 + e[0] - h + a.Pt;
         const int ox = tx0 + e[1] - h + a.Pl;
         const int ag = ox >> 2;      // floor division (arithmetic shift)
@@ -550,46 +555,80 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
     __syncthreads();
     for (int k = 0; k < a.nframes; ++k) {
         const int buf = k & 1;
-        int d_next = 0;
-        if (k + 1 < a.nframes)
-            d_next = fetch(k + 1, pre);
+        // the last iteration re-fetches frame T-1 into the idle buffer: no
+        // branch around the prefetch, so its store stays behind the arithmetic
+        const int d_next = fetch(min(k + 1, a.nframes - 1), pre);
 
-        const int32_t *e = tabj + (size_t)k * TS;
+        const cint32_t *e = tabj + (size_t)k * TS;
         float gy[S], gx[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             gy[s] = __int_as_float(e[2 + s]);
             gx[s] = __int_as_float(e[2 + S + s]);
         }
-        const float *base = reinterpret_cast<const float *>(win4[buf]) + (wv * RPL) * LS +
-                            CPL * lane + d_cur;
+        // One frame of the separable stamp.  ODD is the parity of the lane's
+        // first window column: with an even number of columns per lane it is
+        // the parity of d, and reading 8-byte pairs from the even column at or
+        // before it lets every LDS read use an immediate offset (no address
+        // arithmetic per row).
+        auto frame = [&](auto odd_tag) {
+            constexpr int ODD = decltype(odd_tag)::value;
+            constexpr int NP = (NV + ODD + 1) / 2;
+            const float *wbase = reinterpret_cast<const float *>(win4[buf]) + (wv * RPL) * LS + CPL * lane;
 #pragma unroll
-        for (int rr = 0; rr < RPL + S - 1; ++rr) {
-            float v[NV];
+            for (int rr = 0; rr < RPL + S - 1; ++rr) {
+                float v[NV];
+                if constexpr (CPL % 2 == 0) {
+                    const float2 *p2 = reinterpret_cast<const float2 *>(wbase + (d_cur - ODD) + rr * LS);
+                    float2 pr[NP];
 #pragma unroll
-            for (int t = 0; t < NV; ++t)
-                v[t] = base[rr * LS + t];
-            float hs[CPL];
+                    for (int q = 0; q < NP; ++q)
+                        pr[q] = p2[q];
+                    if constexpr (ODD)   // keep the partly used end pairs 8-byte loads
+                        asm volatile("" : : "v"(pr[0]), "v"(pr[NP - 1]));
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                float sum = gx[0] * v[c];
+                    for (int t = 0; t < NV; ++t)
+                        v[t] = ((t + ODD) & 1) ? pr[(t + ODD) >> 1].y : pr[(t + ODD) >> 1].x;
+                } else {
 #pragma unroll
-                for (int b = 1; b < S; ++b)
-                    sum = fmaf(gx[b], v[c + b], sum);
-                hs[c] = sum;
-            }
+                    for (int t = 0; t < NV; ++t)
+                        v[t] = wbase[d_cur + rr * LS + t];
+                }
+                float hs[CPL];
 #pragma unroll
-            for (int aa = 0; aa < S; ++aa) {
-                const int o = rr - aa;
-                if (o >= 0 && o < RPL) {
+                for (int c = 0; c < CPL; ++c) {
+                    float sum = gx[0] * v[c];
 #pragma unroll
-                    for (int c = 0; c < CPL; ++c)
-                        part[o][c] = fmaf(gy[aa], hs[c], part[o][c]);
+                    for (int b = 1; b < S; ++b)
+                        sum = fmaf(gx[b], v[c + b], sum);
+                    hs[c] = sum;
+                }
+#pragma unroll
+                for (int aa = 0; aa < S; ++aa) {
+                    const int o = rr - aa;
+                    if (o >= 0 && o < RPL) {
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c)
+                            part[o][c] = fmaf(gy[aa], hs[c], part[o][c]);
+                    }
                 }
             }
-        }
-        if (k + 1 < a.nframes)
-            store(buf ^ 1, pre);
+        };
+        if (CPL % 2 == 0 && (d_cur & 1))
+            frame(std::integral_constant<int, 1>{});
+        else
+            frame(std::integral_constant<int, 0>{});
+        // keep the store (and its wait on the prefetch loads) after the
+        // arithmetic, so the loads' latency hides behind it: the empty
+        // volatile asm statements consume every accumulator, and the store
+        // (a side effect) is not moved above them
+#pragma unroll
+        for (int o = 0; o < RPL; ++o)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+                asm volatile("" : "+v"(part[o][c]));
+        __builtin_amdgcn_sched_barrier(0);
+        store(buf ^ 1, pre);
         __syncthreads();
         d_cur = d_next;
         if ((k % FRAME_CHUNK) == FRAME_CHUNK - 1) {
