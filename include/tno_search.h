@@ -110,6 +110,10 @@ typedef struct {
     int32_t n_traj;              /* J >= 1 */
     int32_t top_k;               /* candidates wanted, 0..TNO_MAX_TOPK */
     const double *velocities;    /* [J][2] = (vx, vy) in pixels per unit of `times` */
+    int32_t sig_box;             /* 0: no significance map; else the odd side of the square
+                                    window (e.g. 255) over which the local standard deviation
+                                    of the best-score map is taken (Sec. 3.3) */
+    float sig_threshold;         /* detections: significance >= this (e.g. 3 or 5) */
     uint64_t stack_key;          /* 0, or a key: with residuals, the library keeps a device copy
                                     of residuals, scales and sigma under the key (evicted least
                                     recently used when the budget needs room); with NULL
@@ -131,6 +135,15 @@ typedef struct {
     int32_t traj, y, x;
 } tno_candidate;
 
+/* A detection of the Sec. 3.3 significance test: the pixel's best score over
+ * the bank in units of the local standard deviation of the best-score map. */
+typedef struct {
+    float significance, snr, flux;
+    int32_t traj, y, x;
+} tno_detection;
+
+#define TNO_MAX_DETECTIONS 1024
+
 /* Outputs; every pointer may be NULL (= not produced).  Host or device memory
  * according to TNO_REQ_DEVICE_PTRS.  Caller-owned; written only between a
  * successful submit and the ticket's terminal poll. */
@@ -141,11 +154,20 @@ typedef struct {
     int32_t *best_traj;          /* [H][W] arg-max j */
     tno_peak *traj_max;          /* [J] per-trajectory max, ties to the smallest y*W+x */
     tno_candidate *topk;         /* [top_k] SNR descending, then j*H*W+y*W+x ascending */
+    float *significance;         /* [H][W] best_snr / local std over sig_box x sig_box
+                                    (0 where the std is 0); needs sig_box > 0 */
+    tno_detection *detections;   /* [max_detections] pixels with significance >=
+                                    sig_threshold, significance descending then y*W+x
+                                    ascending; needs sig_box > 0 */
+    int32_t max_detections;      /* capacity of detections, 0..TNO_MAX_DETECTIONS */
+    int32_t reserved;            /* must be 0 */
 } tno_outputs;
 
 typedef struct {
     int32_t status;              /* TNO_OK or a TNO_E_* code */
     int32_t n_topk;              /* candidates written (min(top_k, J*H*W)) */
+    int32_t n_detections;        /* detections written (<= max_detections) */
+    int32_t n_above;             /* pixels with significance >= sig_threshold */
     uint64_t updates;            /* J*H*W*T (trajectory x pixel x frame terms) */
     double queue_ms;             /* total_ms - device_ms (host staging, queueing, polling) */
     double device_ms;            /* device start -> device end (HIP events) */

@@ -219,3 +219,47 @@ def topk(snr, flux, k):
         j, p = divmod(int(o), H * W)
         out.append((float(s[o]), float(f[o]), j, p // W, p % W))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.3: scores in units of the standard deviation of the scores in the
+# box x box square centred on each pixel; candidates above a threshold.
+# ---------------------------------------------------------------------------
+
+def significance(best, box, pixels=None):
+    """Each pixel's best score divided by the (population) standard deviation
+    of the best scores in the box x box window centred on it, the window
+    clipped at the image edges; 0 where that standard deviation is 0.
+    Evaluated window by window; `pixels` = (ys, xs) restricts it to those
+    pixels (returned as a 1-D array), else the whole map is returned."""
+    b = np.asarray(best, np.float64)
+    H, W = b.shape
+    h = int(box) // 2
+    if pixels is None:
+        ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+        ys, xs = ys.ravel(), xs.ravel()
+    else:
+        ys, xs = (np.asarray(v).ravel() for v in pixels)
+    out = np.zeros(ys.size, np.float64)
+    for i, (y, x) in enumerate(zip(ys, xs)):
+        w = b[max(0, y - h):y + h + 1, max(0, x - h):x + h + 1]
+        sd = w.std()
+        out[i] = b[y, x] / sd if sd > 0 else 0.0
+    return out.reshape(H, W) if pixels is None else out
+
+
+def detections(sig, best, best_j, flux, threshold, k):
+    """Pixels with significance >= threshold, ordered by significance
+    descending then y*W + x ascending; the first k as (sig, snr, flux, j, y, x)."""
+    H, W = sig.shape
+    s = sig.reshape(-1)
+    idx = np.arange(s.size)
+    order = np.lexsort((idx, -s))
+    out = []
+    for o in order[:k]:
+        if s[o] < threshold:
+            break
+        y, x = divmod(int(o), W)
+        j = int(best_j[y, x])
+        out.append((float(s[o]), float(best[y, x]), float(flux[j, y, x]), j, y, x))
+    return out

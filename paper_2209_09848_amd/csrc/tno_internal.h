@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/tno_search.h"
+
 namespace tno {
 
 // Search tile shapes.  A lane owns CPL adjacent columns x SEARCH_RPL rows; a
@@ -99,6 +101,11 @@ hipError_t launch_best(hipStream_t st, int J, int HW, const float *snr, float *b
 hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int64_t N, int HW,
                        int W, int k, TopkState *state, uint32_t *chunk_cnt, int64_t n_chunks,
                        uint64_t *cand, void *topk_out);
+hipError_t launch_significance(hipStream_t st, int H, int W, int box, float thr, int k,
+                               const float *best_snr, const int32_t *best_traj, const float *flux,
+                               double *r1, double *r2, float *sig, TopkState *state,
+                               uint32_t *chunk_cnt, int64_t n_chunks, uint64_t *cand,
+                               tno_detection *det, int32_t *counts);
 hipError_t launch_quantize(hipStream_t st, int dtype, const float *R, int T, int H, int W,
                            void *codes, float *scales);
 

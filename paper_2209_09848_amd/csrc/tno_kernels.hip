@@ -16,6 +16,7 @@
 #include <stdint.h>
 #include <limits.h>
 #include <type_traits>
+#include <algorithm>
 
 #include "tno_internal.h"
 #include "../../include/tno_search.h"
@@ -396,22 +397,27 @@ __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
         const int len = m.y;
         if (len == 0)
             continue;
+        // branch-free loads: clamp into the image, then zero what lies outside
         const int X = x + ti.qx0 + c;
         const bool xin = (unsigned)X < (unsigned)a.W;
+        const double *col = a.ivar64 + min(max(X, 0), a.W - 1);
+        // (multiplying by a 0/1 mask, rather than selecting, keeps the load
+        // unconditional; ivar is finite, so 0 * ivar = 0)
+        auto ld = [&](int Y) -> double {
+            const int Yc = min(max(Y, 0), a.H - 1);
+            const double t = col[(size_t)Yc * a.W];
+            return t * ((xin && Y == Yc) ? 1.0 : 0.0);
+        };
         const double *kv = a.kvals + ti.val_off + (int64_t)c * ti.cap;
         const int ybase = y0 + m.x;
         double v[R + C - 1];
 #pragma unroll
-        for (int i = 0; i < R - 1; ++i) {
-            const int Y = ybase + i;
-            v[i] = (xin && (unsigned)Y < (unsigned)a.H) ? a.ivar64[(size_t)Y * a.W + X] : 0.0;
-        }
+        for (int i = 0; i < R - 1; ++i)
+            v[i] = ld(ybase + i);
         for (int q0 = 0; q0 < len; q0 += C) {
 #pragma unroll
-            for (int i = R - 1; i < R + C - 1; ++i) {
-                const int Y = ybase + q0 + i;
-                v[i] = (xin && (unsigned)Y < (unsigned)a.H) ? a.ivar64[(size_t)Y * a.W + X] : 0.0;
-            }
+            for (int i = R - 1; i < R + C - 1; ++i)
+                v[i] = ld(ybase + q0 + i);
             double kc[C];
 #pragma unroll
             for (int t = 0; t < C; ++t)
@@ -957,14 +963,10 @@ __global__ void k_topk_ties(const float *__restrict__ snr, int64_t N, int k,
     }
 }
 
-// Sort the k candidates (key desc, index asc) in LDS and write the output.
-__global__ __launch_bounds__(1024) void k_topk_final(const float *__restrict__ flux, int64_t N,
-                                                     int k, int HW, int W,
-                                                     const uint64_t *__restrict__ cand,
-                                                     tno_candidate *__restrict__ out)
+// Bitonic sort of up to TNO_MAX_TOPK (key, index) pairs in LDS into
+// (key descending, index ascending); one thread per slot, slots >= k padded.
+__device__ void sort_candidates(uint64_t *sk, uint64_t *si, const uint64_t *cand, int k)
 {
-    __shared__ uint64_t sk[TNO_MAX_TOPK];
-    __shared__ uint64_t si[TNO_MAX_TOPK];
     const int t = threadIdx.x;
     // pad with the smallest key and the largest index
     sk[t] = t < k ? cand[2 * t] : 0u;
@@ -985,6 +987,18 @@ __global__ __launch_bounds__(1024) void k_topk_final(const float *__restrict__ f
             __syncthreads();
         }
     }
+}
+
+// Sort the k candidates and write them as (snr, flux, traj, y, x).
+__global__ __launch_bounds__(1024) void k_topk_final(const float *__restrict__ flux, int64_t N,
+                                                     int k, int HW, int W,
+                                                     const uint64_t *__restrict__ cand,
+                                                     tno_candidate *__restrict__ out)
+{
+    __shared__ uint64_t sk[TNO_MAX_TOPK];
+    __shared__ uint64_t si[TNO_MAX_TOPK];
+    const int t = threadIdx.x;
+    sort_candidates(sk, si, cand, k);
     if (t < k) {
         uint64_t idx = si[t] < (uint64_t)N ? si[t] : 0;
         tno_candidate c;
@@ -998,23 +1012,182 @@ __global__ __launch_bounds__(1024) void k_topk_final(const float *__restrict__ f
     }
 }
 
-hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int64_t N, int HW,
-                       int W, int k, TopkState *state, uint32_t *chunk_cnt, int64_t n_chunks,
-                       uint64_t *cand, void *topk_out)
+// Radix select + tie resolution of the k largest keys of `vals` (N values);
+// leaves the k (key, index) pairs, unsorted, in cand.
+static void topk_select(hipStream_t st, const float *vals, int64_t N, int k, TopkState *state,
+                        uint32_t *chunk_cnt, int64_t n_chunks, uint64_t *cand)
 {
     hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(256), 0, st, state, k, cand);
     int64_t blocks = (N + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     for (int pass = 0; pass < 4; ++pass) {
         int shift = 24 - 8 * pass;
-        hipLaunchKernelGGL(k_topk_hist, dim3((unsigned)blocks), dim3(256), 0, st, snr, N, state, shift);
+        hipLaunchKernelGGL(k_topk_hist, dim3((unsigned)blocks), dim3(256), 0, st, vals, N, state, shift);
         hipLaunchKernelGGL(k_topk_select, dim3(1), dim3(256), 0, st, state, shift);
     }
-    hipLaunchKernelGGL(k_topk_gt, dim3((unsigned)n_chunks), dim3(256), 0, st, snr, N, k, state, chunk_cnt, cand);
+    hipLaunchKernelGGL(k_topk_gt, dim3((unsigned)n_chunks), dim3(256), 0, st, vals, N, k, state, chunk_cnt, cand);
     hipLaunchKernelGGL(k_topk_scan, dim3(1), dim3(256), 0, st, chunk_cnt, n_chunks);
-    hipLaunchKernelGGL(k_topk_ties, dim3((unsigned)n_chunks), dim3(256), 0, st, snr, N, k, state, chunk_cnt, cand);
+    hipLaunchKernelGGL(k_topk_ties, dim3((unsigned)n_chunks), dim3(256), 0, st, vals, N, k, state, chunk_cnt, cand);
+}
+
+hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int64_t N, int HW,
+                       int W, int k, TopkState *state, uint32_t *chunk_cnt, int64_t n_chunks,
+                       uint64_t *cand, void *topk_out)
+{
+    topk_select(st, snr, N, k, state, chunk_cnt, n_chunks, cand);
     hipLaunchKernelGGL(k_topk_final, dim3(1), dim3(TNO_MAX_TOPK), 0, st, flux, N, k, HW, W, cand,
                        (tno_candidate *)topk_out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ significance (Sec. 3.3)
+//
+// The paper expresses each pixel's best score in units of the standard
+// deviation of the scores in the box x box square centred on it.  Windows are
+// clipped at the image edges; the std is the population std of the scores
+// inside, from FP64 sliding sums of s and s^2 along rows, then columns; a
+// variance below 1e-12 of the window's mean square counts as 0.
+
+constexpr int BOX_SEG = 64;   // outputs per thread of a sliding pass
+
+__global__ void k_box_rows(int H, int W, int hb, const float *__restrict__ s,
+                           double *__restrict__ r1, double *__restrict__ r2)
+{
+    const int nseg = (W + BOX_SEG - 1) / BOX_SEG;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= H * nseg)
+        return;
+    const int y = gid / nseg, x0 = (gid - y * nseg) * BOX_SEG;
+    const float *row = s + (size_t)y * W;
+    double a1 = 0.0, a2 = 0.0;
+    for (int x = max(0, x0 - hb); x <= min(W - 1, x0 + hb); ++x) {
+        double v = row[x];
+        a1 += v;
+        a2 += v * v;
+    }
+    const int x1 = min(W, x0 + BOX_SEG);
+    for (int x = x0; x < x1; ++x) {
+        if (x > x0) {
+            if (x + hb < W) {
+                double v = row[x + hb];
+                a1 += v;
+                a2 += v * v;
+            }
+            if (x - hb - 1 >= 0) {
+                double v = row[x - hb - 1];
+                a1 -= v;
+                a2 -= v * v;
+            }
+        }
+        r1[(size_t)y * W + x] = a1;
+        r2[(size_t)y * W + x] = a2;
+    }
+}
+
+// Column pass: box sums, counts, std and significance = best / std (0 if std == 0).
+__global__ void k_box_cols(int H, int W, int hb, const double *__restrict__ r1,
+                           const double *__restrict__ r2, const float *__restrict__ s,
+                           float *__restrict__ sig)
+{
+    const int nseg = (H + BOX_SEG - 1) / BOX_SEG;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= W * nseg)
+        return;
+    const int x = gid % W, y0 = (gid / W) * BOX_SEG;   // adjacent threads: adjacent columns
+    const double nx = (double)(min(W - 1, x + hb) - max(0, x - hb) + 1);
+    double a1 = 0.0, a2 = 0.0;
+    for (int y = max(0, y0 - hb); y <= min(H - 1, y0 + hb); ++y) {
+        a1 += r1[(size_t)y * W + x];
+        a2 += r2[(size_t)y * W + x];
+    }
+    const int y1 = min(H, y0 + BOX_SEG);
+    for (int y = y0; y < y1; ++y) {
+        if (y > y0) {
+            if (y + hb < H) {
+                a1 += r1[(size_t)(y + hb) * W + x];
+                a2 += r2[(size_t)(y + hb) * W + x];
+            }
+            if (y - hb - 1 >= 0) {
+                a1 -= r1[(size_t)(y - hb - 1) * W + x];
+                a2 -= r2[(size_t)(y - hb - 1) * W + x];
+            }
+        }
+        const double n = nx * (double)(min(H - 1, y + hb) - max(0, y - hb) + 1);
+        const double mean = a1 / n;
+        const double var = a2 / n - mean * mean;
+        // running sums leave a residue of order 1e-16 of the mean square
+        // where the window is constant: treat such a variance as 0
+        const double sd = var > 1e-12 * (a2 / n) ? sqrt(var) : 0.0;
+        const size_t p = (size_t)y * W + x;
+        float g = sd > 0.0 ? (float)((double)s[p] / sd) : 0.0f;
+        sig[p] = g + 0.0f;
+    }
+}
+
+__global__ void k_count_above(int64_t N, const float *__restrict__ sig, float thr, int32_t *count)
+{
+    uint32_t c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x)
+        c += sig[i] >= thr ? 1u : 0u;
+    for (int off = 32; off >= 1; off >>= 1)
+        c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0 && c)
+        atomicAdd(count, (int32_t)c);
+}
+
+// Sort the k most significant pixels and keep those at or above the threshold.
+__global__ __launch_bounds__(1024) void k_detect_final(
+    int64_t HW, int W, int k, float thr, const uint64_t *__restrict__ cand,
+    const float *__restrict__ best_snr, const int32_t *__restrict__ best_traj,
+    const float *__restrict__ flux, tno_detection *__restrict__ out, int32_t *n_out)
+{
+    __shared__ uint64_t sk[TNO_MAX_TOPK];
+    __shared__ uint64_t si[TNO_MAX_TOPK];
+    __shared__ int32_t n_keep;
+    const int t = threadIdx.x;
+    if (t == 0)
+        n_keep = 0;
+    sort_candidates(sk, si, cand, k);
+    if (t < k) {
+        const float g = key_to_float((uint32_t)sk[t]);
+        if (g >= thr) {
+            const uint64_t p = si[t] < (uint64_t)HW ? si[t] : 0;
+            const int32_t j = best_traj[p];
+            tno_detection d;
+            d.significance = g;
+            d.snr = best_snr[p];
+            d.flux = flux[(uint64_t)j * HW + p];
+            d.traj = j;
+            d.y = (int32_t)(p / (uint64_t)W);
+            d.x = (int32_t)(p % (uint64_t)W);
+            out[t] = d;
+            atomicAdd(&n_keep, 1);
+        }
+    }
+    __syncthreads();
+    if (t == 0)
+        *n_out = n_keep;
+}
+
+hipError_t launch_significance(hipStream_t st, int H, int W, int box, float thr, int k,
+                               const float *best_snr, const int32_t *best_traj, const float *flux,
+                               double *r1, double *r2, float *sig, TopkState *state,
+                               uint32_t *chunk_cnt, int64_t n_chunks, uint64_t *cand,
+                               tno_detection *det, int32_t *counts)
+{
+    const int hb = box / 2;
+    const int nr = H * ((W + BOX_SEG - 1) / BOX_SEG), nc = W * ((H + BOX_SEG - 1) / BOX_SEG);
+    hipLaunchKernelGGL(k_box_rows, dim3((nr + 255) / 256), dim3(256), 0, st, H, W, hb, best_snr, r1, r2);
+    hipLaunchKernelGGL(k_box_cols, dim3((nc + 255) / 256), dim3(256), 0, st, H, W, hb, r1, r2, best_snr, sig);
+    const int64_t HW = (int64_t)H * W;
+    int blocks = (int)std::min<int64_t>((HW + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_count_above, dim3(blocks), dim3(256), 0, st, HW, sig, thr, counts);
+    if (k > 0) {
+        topk_select(st, sig, HW, k, state, chunk_cnt, n_chunks, cand);
+        hipLaunchKernelGGL(k_detect_final, dim3(1), dim3(TNO_MAX_TOPK), 0, st, HW, W, k, thr, cand,
+                           best_snr, best_traj, flux, det, counts + 1);
+    }
     return hipGetLastError();
 }
 

@@ -85,13 +85,16 @@ struct Plan {
     int lntx = 0, lnty = 0;
     int64_t N = 0, n_chunks = 0;
     bool own_snr = true, own_flux = true;
+    int box = 0, kdet = 0;            // significance window side; detections wanted
+    float thr = 0.0f;
     bool stack_in_arena = false;      // host residuals copied into the arena (no stack_key)
     size_t stack_bytes = 0;           // bytes of a resident stack holding these residuals
     // arena layout (byte offsets)
     size_t o_R = 0, o_scales = 0, o_sigma = 0, o_times = 0, o_vel = 0, o_Z = 0, o_iv32 = 0,
            o_iv64 = 0, o_tab32 = 0, o_tab64 = 0, o_trail = 0, o_colmeta = 0, o_kvals = 0,
            o_err = 0, o_lam = 0, o_snr = 0, o_flux = 0, o_tkeys = 0, o_tstate = 0, o_chunks = 0,
-           o_cand = 0, o_tmax = 0, o_topk = 0, o_best = 0, o_bestj = 0, o_perm = 0, bytes = 0;
+           o_cand = 0, o_tmax = 0, o_topk = 0, o_best = 0, o_bestj = 0, o_perm = 0, o_r1 = 0,
+           o_r2 = 0, o_sig = 0, o_det = 0, o_counts = 0, bytes = 0;
 };
 
 bool finite(double v) { return std::isfinite(v); }
@@ -134,6 +137,18 @@ Fail check_shape(const tno_request *r, const tno_outputs *o)
         return fail(TNO_E_INVAL, "top_k must be in 0..%d", TNO_MAX_TOPK);
     if (r->top_k > 0 && !o->topk)
         return fail(TNO_E_INVAL, "top_k > 0 needs outputs.topk");
+    if (o->reserved != 0)
+        return fail(TNO_E_INVAL, "outputs.reserved must be 0");
+    if (r->sig_box < 0 || r->sig_box > 65535 || (r->sig_box > 0 && r->sig_box % 2 == 0))
+        return fail(TNO_E_INVAL, "sig_box must be 0 or odd and <= 65535");
+    if (r->sig_box > 0 && !std::isfinite(r->sig_threshold))
+        return fail(TNO_E_INVAL, "sig_threshold must be finite");
+    if (o->max_detections < 0 || o->max_detections > TNO_MAX_DETECTIONS)
+        return fail(TNO_E_INVAL, "max_detections must be in 0..%d", TNO_MAX_DETECTIONS);
+    if (o->max_detections > 0 && !o->detections)
+        return fail(TNO_E_INVAL, "max_detections > 0 needs outputs.detections");
+    if ((o->significance || o->max_detections > 0) && r->sig_box == 0)
+        return fail(TNO_E_INVAL, "significance outputs need sig_box > 0");
     if ((r->flags & ~(TNO_REQ_DEVICE_PTRS | TNO_REQ_VALIDATE)) != 0)
         return fail(TNO_E_INVAL, "unknown request flags 0x%x", r->flags);
     if (!finite(r->t_ref) && !std::isnan(r->t_ref))
@@ -272,6 +287,9 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     p.N = (int64_t)p.J * H * W;
     p.k = (int)std::min<int64_t>(r->top_k, p.N);
     p.n_chunks = (p.N + tno::TOPK_CHUNK - 1) / tno::TOPK_CHUNK;
+    p.box = r->sig_box;
+    p.thr = r->sig_threshold;
+    p.kdet = (int)std::min<int64_t>(o->max_detections, (int64_t)p.H * p.W);
     p.own_snr = !(p.dev && o->snr);
     p.own_flux = !(p.dev && o->flux);
 
@@ -320,6 +338,13 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     p.o_topk = take((size_t)TNO_MAX_TOPK * sizeof(tno_candidate));
     p.o_best = take(HW * 4);
     p.o_bestj = take(HW * 4);
+    p.o_counts = take(16);
+    if (p.box > 0) {
+        p.o_r1 = take(HW * 8);
+        p.o_r2 = take(HW * 8);
+        p.o_sig = take(HW * 4);
+        p.o_det = take((size_t)TNO_MAX_DETECTIONS * sizeof(tno_detection));
+    }
     p.bytes = off;
     return fail(TNO_OK, "");
 }
@@ -633,8 +658,21 @@ hipError_t enqueue_back(Request *q)
         TRY(tno::launch_topk(st, snr, flux, p.N, HW, p.W, p.k, at<tno::TopkState>(A, p.o_tstate),
                              at<uint32_t>(A, p.o_chunks), p.n_chunks, at<uint64_t>(A, p.o_cand),
                              at<void>(A, p.o_topk)));
+    TRY(tno::launch_zero(st, at<int32_t>(A, p.o_counts), 4));
+    if (p.box > 0)
+        TRY(tno::launch_significance(st, p.H, p.W, p.box, p.thr, p.kdet, at<float>(A, p.o_best),
+                                     at<int32_t>(A, p.o_bestj), flux, at<double>(A, p.o_r1),
+                                     at<double>(A, p.o_r2), at<float>(A, p.o_sig),
+                                     at<tno::TopkState>(A, p.o_tstate), at<uint32_t>(A, p.o_chunks),
+                                     p.n_chunks, at<uint64_t>(A, p.o_cand),
+                                     at<tno_detection>(A, p.o_det), at<int32_t>(A, p.o_counts)));
     if (p.dev) {
         const tno_outputs &o = q->out;
+        if (o.significance && p.box > 0)
+            TRY(hipMemcpyAsync(o.significance, at<void>(A, p.o_sig), (size_t)HW * 4, hipMemcpyDeviceToDevice, st));
+        if (o.detections && p.kdet > 0)
+            TRY(hipMemcpyAsync(o.detections, at<void>(A, p.o_det), (size_t)p.kdet * sizeof(tno_detection),
+                               hipMemcpyDeviceToDevice, st));
         if (o.traj_max)
             TRY(hipMemcpyAsync(o.traj_max, at<void>(A, p.o_tmax), (size_t)p.J * sizeof(tno_peak),
                                hipMemcpyDeviceToDevice, st));
@@ -755,6 +793,11 @@ hipError_t finish_outputs(Request *q)
     cp(o.traj_max, p.o_tmax, J * sizeof(tno_peak));
     if (p.k > 0)
         cp(o.topk, p.o_topk, (size_t)p.k * sizeof(tno_candidate));
+    if (p.box > 0) {
+        cp(o.significance, p.o_sig, HW * 4);
+        if (p.kdet > 0)
+            cp(o.detections, p.o_det, (size_t)p.kdet * sizeof(tno_detection));
+    }
     return e;
 }
 
@@ -1080,8 +1123,12 @@ int tno_search_poll(tno_search *h, uint64_t ticket, int32_t timeout_ms, tno_resu
                 for (int i = 0; i < 5; ++i)
                     if (hipEventElapsedTime(&ms, q->ev[i], q->ev[i + 1]) == hipSuccess)
                         *ph[i] = ms;
-                int32_t err = 0;
+                int32_t err = 0, counts[4] = {0, 0, 0, 0};
                 hipError_t e2 = hipMemcpy(&err, at<void>(q->arena, q->plan.o_err), 4, hipMemcpyDeviceToHost);
+                if (e2 == hipSuccess)
+                    e2 = hipMemcpy(counts, at<void>(q->arena, q->plan.o_counts), 16, hipMemcpyDeviceToHost);
+                res.n_above = counts[0];
+                res.n_detections = counts[1];
                 if (e2 == hipSuccess && !err)
                     e2 = finish_outputs(q);
                 if (e2 != hipSuccess) {

@@ -33,6 +33,7 @@ SEARCH_VARIANTS = ("w4c2", "w8c2", "w2c2", "w4c1", "w8c1", "w4c4")
 TNO_REQ_DEVICE_PTRS = 1
 TNO_REQ_VALIDATE = 2
 TNO_MAX_TOPK = 1024
+TNO_MAX_DETECTIONS = 1024
 TNO_MAX_STAMP = 15
 TNO_QTILE = 64
 
@@ -56,7 +57,8 @@ class tno_request(ctypes.Structure):
                 ("n_frames", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("residuals", _vp), ("tile_scales", _vp), ("sigma", _vp), ("times", _vp),
                 ("t_ref", ctypes.c_double), ("prf", tno_prf), ("n_traj", ctypes.c_int32),
-                ("top_k", ctypes.c_int32), ("velocities", _vp), ("stack_key", ctypes.c_uint64),
+                ("top_k", ctypes.c_int32), ("velocities", _vp), ("sig_box", ctypes.c_int32),
+                ("sig_threshold", ctypes.c_float), ("stack_key", ctypes.c_uint64),
                 ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
@@ -70,13 +72,21 @@ class tno_candidate(ctypes.Structure):
                 ("y", ctypes.c_int32), ("x", ctypes.c_int32)]
 
 
+class tno_detection(ctypes.Structure):
+    _fields_ = [("significance", ctypes.c_float), ("snr", ctypes.c_float),
+                ("flux", ctypes.c_float), ("traj", ctypes.c_int32), ("y", ctypes.c_int32),
+                ("x", ctypes.c_int32)]
+
+
 class tno_outputs(ctypes.Structure):
     _fields_ = [("snr", _vp), ("flux", _vp), ("best_snr", _vp), ("best_traj", _vp),
-                ("traj_max", _vp), ("topk", _vp)]
+                ("traj_max", _vp), ("topk", _vp), ("significance", _vp), ("detections", _vp),
+                ("max_detections", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class tno_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_topk", ctypes.c_int32),
+                ("n_detections", ctypes.c_int32), ("n_above", ctypes.c_int32),
                 ("updates", ctypes.c_uint64), ("queue_ms", ctypes.c_double),
                 ("device_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("prep_ms", ctypes.c_double), ("table_ms", ctypes.c_double),
@@ -182,7 +192,8 @@ def _ptr(t):
 
 def make_request(R, sigma, times, vel, *, t_ref=float("nan"), dtype="f32", scales=None,
                  sigma_px=0.7, stamp=5, prf_kind=TNO_PRF_GAUSS_SAMPLED, top_k=10,
-                 stack_key=0, flags=TNO_REQ_DEVICE_PTRS, shape=None) -> tno_request:
+                 stack_key=0, flags=TNO_REQ_DEVICE_PTRS, shape=None, sig_box=0,
+                 sig_threshold=5.0) -> tno_request:
     """A request over torch tensors on the GPU (device pointers).  R may be
     None (search the stack resident under stack_key) with shape=(T, H, W)."""
     T, H, W = (int(s) for s in (R.shape if R is not None else shape))
@@ -198,6 +209,8 @@ def make_request(R, sigma, times, vel, *, t_ref=float("nan"), dtype="f32", scale
     req.n_traj = int(vel.shape[0])
     req.top_k = int(top_k)
     req.velocities = _ptr(vel)
+    req.sig_box = int(sig_box)
+    req.sig_threshold = float(sig_threshold)
     req.stack_key = int(stack_key)
     req.flags = int(flags)
     req.reserved = 0
@@ -269,8 +282,10 @@ def shape_class(H, W, T, J, stamp=5) -> str:
     return "S%d_H%d_W%d_J%d_T%d" % (stamp, lg(H), lg(W), lg(J), lg(T))
 
 
-def alloc_outputs(J, H, W, k, device="cuda", maps=True):
-    """Torch output buffers and the tno_outputs struct that points at them."""
+def alloc_outputs(J, H, W, k, device="cuda", maps=True, detections=0):
+    """Torch output buffers and the tno_outputs struct that points at them.
+    detections > 0 also allocates the significance map and that many
+    detection slots (the request needs sig_box > 0)."""
     import torch
     o = {}
     if maps:
@@ -287,7 +302,22 @@ def alloc_outputs(J, H, W, k, device="cuda", maps=True):
     out.best_traj = _ptr(o["best_traj"])
     out.traj_max = _ptr(o["traj_max"])
     out.topk = _ptr(o["topk"]) if k > 0 else None
+    if detections > 0:
+        o["significance"] = torch.empty((H, W), dtype=torch.float32, device=device)
+        o["detections"] = torch.empty((detections, 6), dtype=torch.int32, device=device)
+        out.significance = _ptr(o["significance"])
+        out.detections = _ptr(o["detections"])
+        out.max_detections = int(detections)
     return o, out
+
+
+def decode_detections(t, n):
+    """[m][6] int32 tensor of tno_detection -> list of (significance, snr, flux, traj, y, x)."""
+    import numpy as np
+    a = t.cpu().numpy()[:n]
+    f = a[:, :3].copy().view(np.float32)
+    return [(float(f[i, 0]), float(f[i, 1]), float(f[i, 2]), int(a[i, 3]), int(a[i, 4]),
+             int(a[i, 5])) for i in range(n)]
 
 
 def decode_peaks(t):
@@ -308,11 +338,11 @@ def decode_candidates(t, n):
 
 
 def search_tensors(R, sigma, times, vel, *, top_k=10, maps=True, handle: Search | None = None,
-                   **kw):
+                   detections=0, **kw):
     """Run one search over GPU tensors; returns (outputs dict, tno_result)."""
     T, H, W = (int(s) for s in R.shape)
     J = int(vel.shape[0])
-    o, out = alloc_outputs(J, H, W, top_k, device=R.device, maps=maps)
+    o, out = alloc_outputs(J, H, W, top_k, device=R.device, maps=maps, detections=detections)
     req = make_request(R, sigma, times, vel, top_k=top_k, **kw)
     own = handle is None
     h = Search(R.device.index or 0) if own else handle

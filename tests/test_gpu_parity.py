@@ -433,3 +433,84 @@ def test_autotune_writes_cache_and_keeps_results(tmp_path):
     arch, cls, name, tb, rate = lines[0].split()
     assert arch == _arch() and cls == tno.shape_class(100, 260, 60, 20)
     assert name in tno.SEARCH_VARIANTS and 1 <= int(tb) <= 20 and float(rate) > 0
+
+
+# ------------------------------------------------------------------ Sec. 3.3 significance (next row)
+
+SIG_TOL = 3e-5   # SNR inputs within 1e-5 relative; the local std inherits the same order
+
+
+def _sig_check(R, sigma, times, vel, box, thr, k=64, top_k=5):
+    print("significance case: T,H,W=%s J=%d box=%d thr=%g" % (tuple(R.shape), vel.shape[0], box, thr), flush=True)
+    o, res = tno.search_tensors(_to(R), _to(sigma), _to(times), _to(vel), t_ref=float(times[0]),
+                                top_k=top_k, sig_box=box, sig_threshold=thr, detections=k)
+    torch.cuda.synchronize()
+    assert res.status == 0
+    ora = oracle.search(R, sigma, times, float(times[0]), vel)
+    best, bj, _ = oracle.best_over_trajectories(ora["snr"], ora["flux"])
+    osig = oracle.significance(best, box)
+    gsig = o["significance"].cpu().numpy()
+    err = np.abs(gsig - osig) / np.maximum(1.0, np.abs(osig))
+    assert err.max() <= SIG_TOL, err.max()
+    assert res.n_above == int(np.sum(gsig >= thr))
+    band = SIG_TOL * np.maximum(1.0, np.abs(osig))
+    assert np.all((osig >= thr + band) <= (gsig >= thr)) and np.all((gsig >= thr) <= (osig >= thr - band))
+    dets = tno.decode_detections(o["detections"], res.n_detections)
+    assert res.n_detections == min(k, res.n_above)
+    H, W = best.shape
+    gflat = gsig.reshape(-1)
+    ref_order = np.lexsort((np.arange(gflat.size), -gflat))[:res.n_detections]
+    assert [d[4] * W + d[5] for d in dets] == ref_order.tolist()   # GPU order of its own map
+    for d in dets:
+        y, x = d[4], d[5]
+        assert d[0] == gsig[y, x] and d[0] >= thr
+        assert abs(d[1] - best[y, x]) <= 1e-5 * max(1.0, abs(best[y, x]))
+        assert abs(ora["snr"][d[3], y, x] - best[y, x]) <= 2e-5 * max(1.0, abs(best[y, x]))
+    return gsig, osig, dets
+
+
+def test_significance_tiny_config():
+    p = synth.make_c1("bright")
+    gsig, osig, dets = _sig_check(p.R, p.sigma, p.times, p.vel, 31, 3.0)
+    assert dets and abs(dets[0][4] - 32) <= 2 and abs(dets[0][5] - 20) <= 2
+
+
+@pytest.mark.parametrize("box", [1, 15, 255])
+def test_significance_ragged_and_clipped_windows(box):
+    R, sigma, times, vel = _rand_problem(90 + box, 7, 45, 150, 3)
+    sigma[10:30, 60:120] = 0.0          # masked block: Lam = 0, scores exactly 0
+    R[:, 20, 40] += 50.0                # one bright pixel
+    gsig, osig, dets = _sig_check(R, sigma, times, vel, box, 2.5)
+    if box == 1:
+        assert np.all(gsig == 0)
+
+
+def test_significance_full_size_property():
+    """FFI size: significance * (population std of the best map over the
+    255 x 255 clipped window, computed here independently) = best score."""
+    from scipy import ndimage
+    H = W = 2048
+    R, sigma, times, t_ref, vel, src = synth.make_ffi_like_torch(H, W, 1000, DEV)
+    o, res = tno.search_tensors(R, _to(sigma), _to(times), _to(vel), t_ref=t_ref, top_k=10,
+                                sig_box=255, sig_threshold=5.0, detections=256, maps=False)
+    torch.cuda.synchronize()
+    best = o["best_snr"].cpu().numpy().astype(np.float64)
+    gsig = o["significance"].cpu().numpy()
+    ones = np.ones_like(best)
+    n = ndimage.uniform_filter(ones, 255, mode="constant") * 255 ** 2
+    s1 = ndimage.uniform_filter(best, 255, mode="constant") * 255 ** 2
+    s2 = ndimage.uniform_filter(best * best, 255, mode="constant") * 255 ** 2
+    sd = np.sqrt(np.maximum(s2 / n - (s1 / n) ** 2, 0))
+    ref = best / sd
+    err = np.abs(gsig - ref) / np.maximum(1.0, np.abs(ref))
+    assert err.max() <= 1e-5
+    assert res.n_above == int(np.sum(gsig >= 5.0))
+    dets = tno.decode_detections(o["detections"], res.n_detections)
+    assert res.n_detections == min(256, res.n_above)
+    # injected sources bright enough in SNR come out as detections near their start
+    found = 0
+    for s in src:
+        yr, xr = int(round(s.y)), int(round(s.x))
+        if gsig[max(0, yr - 1):yr + 2, max(0, xr - 1):xr + 2].max() >= 5.0:
+            found += any(abs(d[4] - yr) <= 1 and abs(d[5] - xr) <= 1 for d in dets)
+    print("sources detected at 5 sigma:", found, "of", len(src), "; pixels above:", res.n_above, flush=True)

@@ -341,3 +341,59 @@ def test_reductions_against_plain_loops(oracle_mod):
     ref = sorted(((snr[j, yy, xx], j * H * W + yy * W + xx) for j in range(J)
                   for yy in range(H) for xx in range(W)), key=lambda t: (-t[0], t[1]))[:17]
     assert [(c[0], c[2] * H * W + c[3] * W + c[4]) for c in tk] == ref
+
+
+# ------------------------------------------------------------------ Sec. 3.3 significance
+
+@pytest.mark.parametrize("H,W,box", [(23, 31, 7), (17, 12, 63), (40, 40, 1), (33, 45, 15)])
+def test_significance_is_local_std_definition(oracle_mod, H, W, box):
+    """Direct definition: np.std over each clipped window."""
+    g = np.random.default_rng(H * W + box)
+    b = g.standard_normal((H, W)) * (1 + g.random((H, W)))
+    got = oracle_mod.significance(b, box)
+    h = box // 2
+    for y in range(H):
+        for x in range(W):
+            w = b[max(0, y - h):y + h + 1, max(0, x - h):x + h + 1]
+            sd = w.std()
+            ref = b[y, x] / sd if sd > 0 else 0.0
+            assert abs(got[y, x] - ref) <= 1e-10 * max(1.0, abs(ref))
+
+
+def test_significance_interior_matches_uniform_filter(oracle_mod):
+    g = np.random.default_rng(3)
+    b = g.standard_normal((60, 70))
+    box = 31
+    m1 = ndimage.uniform_filter(b, box, mode="constant")
+    m2 = ndimage.uniform_filter(b * b, box, mode="constant")
+    sd = np.sqrt(m2 - m1 * m1)
+    got = oracle_mod.significance(b, box)
+    h = box // 2
+    np.testing.assert_allclose(got[h:-h, h:-h], (b / sd)[h:-h, h:-h], rtol=1e-9)
+
+
+def test_significance_invariants(oracle_mod):
+    g = np.random.default_rng(4)
+    b = g.standard_normal((30, 30))
+    s = oracle_mod.significance(b, 9)
+    np.testing.assert_allclose(oracle_mod.significance(3.5 * b, 9), s, rtol=1e-12)
+    assert np.all(oracle_mod.significance(np.full((10, 10), 2.0), 5) == 0)
+    # a white-noise map's significance is ~ N(0,1) (sampled pixels)
+    big = g.standard_normal((400, 400))
+    ys, xs = np.meshgrid(np.arange(25, 375, 7), np.arange(25, 375, 7), indexing="ij")
+    v = oracle_mod.significance(big, 51, pixels=(ys, xs))
+    assert abs(v.mean()) < 0.05 and abs(v.std() - 1.0) < 0.05
+    full = oracle_mod.significance(big[:40, :50], 9)
+    np.testing.assert_allclose(oracle_mod.significance(big[:40, :50], 9, pixels=([3, 39], [0, 49])),
+                               [full[3, 0], full[39, 49]], rtol=0)
+
+
+def test_detections_order_and_threshold(oracle_mod):
+    sig = np.array([[1.0, 5.0, 3.0], [5.0, 2.9, 4.0]])
+    best = sig * 2
+    bj = np.array([[0, 1, 0], [1, 1, 0]])
+    flux = np.stack([sig, sig + 10])
+    d = oracle_mod.detections(sig, best, bj, flux, 3.0, 10)
+    assert [(t[4], t[5]) for t in d] == [(0, 1), (1, 0), (1, 2), (0, 2)]
+    assert d[0][2] == 15.0 and d[2][2] == 4.0
+    assert len(oracle_mod.detections(sig, best, bj, flux, 3.0, 2)) == 2
