@@ -17,12 +17,22 @@
  *
  *     ivar(y,x)   = 1/sigma(y,x)^2 if sigma finite and > 0, else 0
  *                   (masked / clipped pixels, Sec. 3.2), 0 off the image
- *     D_k         = v * (t_k - t_ref)                     (per axis, FP64)
+ *     D_k         = v * (t_k - t_ref) + theta_k           (per axis, FP64;
+ *                   theta_k = pointing jitter of frame k, Sec. 2.2 / 3.1,
+ *                   folded into the filter as Sec. 3.2 says; 0 if absent)
  *     i_k         = floor(D_k + 1/2),  f_k = D_k - i_k    (anchor, phase)
+ *   Gaussian PRF (separable):
  *     g(b; f)     = exp(-(b - f)^2 / (2 sp^2))            (sampled Gaussian)
  *              or = Phi((b+1/2-f)/sp) - Phi((b-1/2-f)/sp) (pixel-integrated)
  *     ghat        = g / sum_b g                           b = -h..h, S = 2h+1
  *     W_k(a,b)    = ghat(a; f_y,k) * ghat(b; f_x,k)       a = row, b = column
+ *   Tabulated PRF (Sec. 2.1: the PRF gives the share of a point source's
+ *   flux that each pixel records; not separable in general):
+ *     P(u_y, u_x) = the share recorded by a pixel whose centre lies at offset
+ *                   (u_y, u_x) from the source, tabulated on the grid
+ *                   u = -(h+1) + i/q, i = 0 .. (S+1)q, and read between grid
+ *                   points by bilinear interpolation
+ *     W_k(a,b)    = P(a - f_y,k, b - f_x,k)               (used as given)
  *     nu(y0,x0)   = sum_k sum_ab W_k(a,b) R_k(Y,X) ivar(Y,X)
  *     Lam(y0,x0)  = sum_k sum_ab W_k(a,b)^2 ivar(Y,X)
  *                   with Y = y0 + i_y,k + a, X = x0 + i_x,k + b
@@ -39,6 +49,8 @@
 
 #define ORACLE_PRF_SAMPLED 0
 #define ORACLE_PRF_INTEGRATED 1
+#define ORACLE_PRF_TABLE 2
+#define ORACLE_MAX_S 31
 
 /* Standard normal CDF difference Phi(hi) - Phi(lo), with erfc in the tails
  * so that the far taps of wide stamps keep their relative accuracy. */
@@ -52,11 +64,12 @@ static double phi_diff(double lo, double hi)
     return 0.5 * (erf(hi * r2) - erf(lo * r2));
 }
 
-/* Integer anchor and sub-pixel phase of displacement v*dt (reading: pixel
- * centres sit at integers, the anchor rounds half up, phase in [-1/2, 1/2)). */
-void oracle_offset(double v, double dt, int32_t *i_out, double *f_out)
+/* Integer anchor and sub-pixel phase of displacement v*dt + th (reading:
+ * pixel centres sit at integers, the anchor rounds half up, phase in
+ * [-1/2, 1/2)). */
+void oracle_offset(double v, double dt, double th, int32_t *i_out, double *f_out)
 {
-    double d = v * dt;
+    double d = v * dt + th;
     double a = floor(d + 0.5);
     *i_out = (int32_t)a;
     *f_out = d - a;
@@ -82,18 +95,67 @@ void oracle_profile(int kind, double sp, int S, double f, double *g)
         g[b] = g[b] / sum;
 }
 
+/* Tabulated PRF at offset (uy, ux) by bilinear interpolation of the grid
+ * tab[(S+1)q+1][(S+1)q+1], row-major, rows along y.  For |u| <= h + 1/2 the
+ * cell index stays inside the grid. */
+static double table_value(const double *tab, int S, int q, double uy, double ux)
+{
+    const int n = (S + 1) * q + 1;
+    const double r = (double)(S / 2 + 1);
+    double gy = (uy + r) * (double)q;
+    double gx = (ux + r) * (double)q;
+    double cy = floor(gy), cx = floor(gx);
+    double ty = gy - cy, tx = gx - cx;
+    int i = (int)cy, m = (int)cx;
+    const double *r0 = tab + (size_t)i * n;
+    const double *r1 = r0 + n;
+    double top = (1.0 - tx) * r0[m] + tx * r0[m + 1];
+    double bot = (1.0 - tx) * r1[m] + tx * r1[m + 1];
+    return (1.0 - ty) * top + ty * bot;
+}
+
+/* Stamp weights W(a, b) at phase (fy, fx): w[(a+h)*S + (b+h)]. */
+void oracle_weights(int kind, double sp, int S, const double *tab, int q, double fy,
+                    double fx, double *w)
+{
+    int h = S / 2;
+    if (kind == ORACLE_PRF_TABLE) {
+        for (int a = -h; a <= h; ++a)
+            for (int b = -h; b <= h; ++b)
+                w[(a + h) * S + (b + h)] = table_value(tab, S, q, (double)a - fy, (double)b - fx);
+        return;
+    }
+    double gy[ORACLE_MAX_S], gx[ORACLE_MAX_S];
+    oracle_profile(kind, sp, S, fy, gy);
+    oracle_profile(kind, sp, S, fx, gx);
+    for (int a = 0; a < S; ++a)
+        for (int b = 0; b < S; ++b)
+            w[a * S + b] = gy[a] * gx[b];
+}
+
 /* Offsets and phases of every (trajectory j, frame k):
- * iy, ix [J][T] int32 ; fy, fx [J][T] double.  vel is [J][2] = (vx, vy). */
+ * iy, ix [J][T] int32 ; fy, fx [J][T] double.  vel is [J][2] = (vx, vy);
+ * jit is [T][2] = (theta_x, theta_y) or NULL. */
 void oracle_offsets(int T, const double *times, double t_ref, int J,
-                    const double *vel, int32_t *iy, int32_t *ix,
+                    const double *vel, const double *jit, int32_t *iy, int32_t *ix,
                     double *fy, double *fx)
 {
     for (int j = 0; j < J; ++j)
         for (int k = 0; k < T; ++k) {
             double dt = times[k] - t_ref;
-            oracle_offset(vel[2 * j + 0], dt, &ix[(size_t)j * T + k], &fx[(size_t)j * T + k]);
-            oracle_offset(vel[2 * j + 1], dt, &iy[(size_t)j * T + k], &fy[(size_t)j * T + k]);
+            double thx = jit ? jit[2 * k + 0] : 0.0, thy = jit ? jit[2 * k + 1] : 0.0;
+            oracle_offset(vel[2 * j + 0], dt, thx, &ix[(size_t)j * T + k], &fx[(size_t)j * T + k]);
+            oracle_offset(vel[2 * j + 1], dt, thy, &iy[(size_t)j * T + k], &fy[(size_t)j * T + k]);
         }
+}
+
+static int prf_ok(int kind, double sp, int S, const double *tab, int q)
+{
+    if (S < 1 || S > ORACLE_MAX_S || (S % 2) == 0)
+        return 0;
+    if (kind == ORACLE_PRF_TABLE)
+        return tab != NULL && q >= 1 && q <= 256;
+    return (kind == ORACLE_PRF_SAMPLED || kind == ORACLE_PRF_INTEGRATED) && sp > 0.0;
 }
 
 static double *make_ivar(int H, int W, const float *sigma)
@@ -114,11 +176,11 @@ static double *make_ivar(int H, int W, const float *sigma)
  * arguments / allocation failure. */
 int oracle_search(int H, int W, int T, const float *R, const float *sigma,
                   const double *times, double t_ref, int J, const double *vel,
-                  int kind, double sp, int S,
+                  const double *jit, int kind, double sp, int S, const double *tab, int q,
                   int y_lo, int y_hi, int x_lo, int x_hi,
                   double *nu, double *lam)
 {
-    if (H <= 0 || W <= 0 || T <= 0 || J < 0 || S < 1 || S > 31 || (S % 2) == 0)
+    if (H <= 0 || W <= 0 || T <= 0 || J < 0 || !prf_ok(kind, sp, S, tab, q))
         return -1;
     if (y_lo < 0 || y_hi > H || y_lo > y_hi || x_lo < 0 || x_hi > W || x_lo > x_hi)
         return -1;
@@ -132,17 +194,17 @@ int oracle_search(int H, int W, int T, const float *R, const float *sigma,
 
 #pragma omp parallel for schedule(dynamic, 1)
     for (int j = 0; j < J; ++j) {
-        double gy[31], gx[31];
+        double wt[ORACLE_MAX_S * ORACLE_MAX_S];
         double *nuj = nu + (size_t)j * ny * nx;
         double *lamj = lam + (size_t)j * ny * nx;
         for (int k = 0; k < T; ++k) {
             int32_t iy, ix;
             double fy, fx;
             double dt = times[k] - t_ref;
-            oracle_offset(vel[2 * j + 0], dt, &ix, &fx);
-            oracle_offset(vel[2 * j + 1], dt, &iy, &fy);
-            oracle_profile(kind, sp, S, fy, gy);
-            oracle_profile(kind, sp, S, fx, gx);
+            double thx = jit ? jit[2 * k + 0] : 0.0, thy = jit ? jit[2 * k + 1] : 0.0;
+            oracle_offset(vel[2 * j + 0], dt, thx, &ix, &fx);
+            oracle_offset(vel[2 * j + 1], dt, thy, &iy, &fy);
+            oracle_weights(kind, sp, S, tab, q, fy, fx, wt);
             const float *Rk = R + (size_t)k * H * W;
             for (int a = -h; a <= h; ++a) {
                 for (int y0 = y_lo; y0 < y_hi; ++y0) {
@@ -150,7 +212,7 @@ int oracle_search(int H, int W, int T, const float *R, const float *sigma,
                     if (Y < 0 || Y >= H)
                         continue;
                     for (int b = -h; b <= h; ++b) {
-                        double w = gy[a + h] * gx[b + h];
+                        double w = wt[(a + h) * S + (b + h)];
                         double w2 = w * w;
                         for (int x0 = x_lo; x0 < x_hi; ++x0) {
                             long X = (long)x0 + ix + b;
@@ -173,49 +235,49 @@ int oracle_search(int H, int W, int T, const float *R, const float *sigma,
 /* The same sums for an explicit list of n hypotheses (j, y0, x0). */
 int oracle_hypotheses(int H, int W, int T, const float *R, const float *sigma,
                       const double *times, double t_ref, int J, const double *vel,
-                      int kind, double sp, int S, int n,
-                      const int32_t *hj, const int32_t *hy, const int32_t *hx,
+                      const double *jit, int kind, double sp, int S, const double *tab,
+                      int q, int n, const int32_t *hj, const int32_t *hy, const int32_t *hx,
                       double *nu, double *lam)
 {
-    if (H <= 0 || W <= 0 || T <= 0 || S < 1 || S > 31 || (S % 2) == 0)
+    if (H <= 0 || W <= 0 || T <= 0 || !prf_ok(kind, sp, S, tab, q))
         return -1;
-    for (int q = 0; q < n; ++q)
-        if (hj[q] < 0 || hj[q] >= J || hy[q] < 0 || hy[q] >= H || hx[q] < 0 || hx[q] >= W)
+    for (int e = 0; e < n; ++e)
+        if (hj[e] < 0 || hj[e] >= J || hy[e] < 0 || hy[e] >= H || hx[e] < 0 || hx[e] >= W)
             return -1;
     const int h = S / 2;
 #pragma omp parallel for schedule(dynamic, 4)
-    for (int q = 0; q < n; ++q) {
-        double gy[31], gx[31];
-        int j = hj[q];
+    for (int e = 0; e < n; ++e) {
+        double wt[ORACLE_MAX_S * ORACLE_MAX_S];
+        int j = hj[e];
         double snu = 0.0, slam = 0.0;
         for (int k = 0; k < T; ++k) {
             int32_t iy, ix;
             double fy, fx;
             double dt = times[k] - t_ref;
-            oracle_offset(vel[2 * j + 0], dt, &ix, &fx);
-            oracle_offset(vel[2 * j + 1], dt, &iy, &fy);
-            oracle_profile(kind, sp, S, fy, gy);
-            oracle_profile(kind, sp, S, fx, gx);
+            double thx = jit ? jit[2 * k + 0] : 0.0, thy = jit ? jit[2 * k + 1] : 0.0;
+            oracle_offset(vel[2 * j + 0], dt, thx, &ix, &fx);
+            oracle_offset(vel[2 * j + 1], dt, thy, &iy, &fy);
+            oracle_weights(kind, sp, S, tab, q, fy, fx, wt);
             const float *Rk = R + (size_t)k * H * W;
             for (int a = -h; a <= h; ++a) {
-                long Y = (long)hy[q] + iy + a;
+                long Y = (long)hy[e] + iy + a;
                 if (Y < 0 || Y >= H)
                     continue;
                 for (int b = -h; b <= h; ++b) {
-                    long X = (long)hx[q] + ix + b;
+                    long X = (long)hx[e] + ix + b;
                     if (X < 0 || X >= W)
                         continue;
                     size_t p = (size_t)Y * W + (size_t)X;
                     double s = (double)sigma[p];
                     double iv = (isfinite(s) && s > 0.0) ? 1.0 / (s * s) : 0.0;
-                    double w = gy[a + h] * gx[b + h];
+                    double w = wt[(a + h) * S + (b + h)];
                     snu += w * ((double)Rk[p] * iv);
                     slam += (w * w) * iv;
                 }
             }
         }
-        nu[q] = snu;
-        lam[q] = slam;
+        nu[e] = snu;
+        lam[e] = slam;
     }
     return 0;
 }

@@ -29,6 +29,7 @@ _LIB = os.path.join(_BUILD, "liboracle.so")
 
 PRF_SAMPLED = 0
 PRF_INTEGRATED = 1
+PRF_TABLE = 2
 
 _lock = threading.Lock()
 _lib = None
@@ -54,17 +55,19 @@ def _load():
             lib = ctypes.CDLL(_LIB)
             P = ctypes.POINTER
             d, i32 = ctypes.c_double, ctypes.c_int32
-            lib.oracle_offset.argtypes = [d, d, P(i32), P(d)]
+            lib.oracle_offset.argtypes = [d, d, d, P(i32), P(d)]
             lib.oracle_profile.argtypes = [ctypes.c_int, d, ctypes.c_int, d, P(d)]
-            lib.oracle_offsets.argtypes = [ctypes.c_int, P(d), d, ctypes.c_int, P(d),
+            lib.oracle_weights.argtypes = [ctypes.c_int, d, ctypes.c_int, P(d), ctypes.c_int,
+                                           d, d, P(d)]
+            lib.oracle_offsets.argtypes = [ctypes.c_int, P(d), d, ctypes.c_int, P(d), P(d),
                                            P(i32), P(i32), P(d), P(d)]
             lib.oracle_search.argtypes = [ctypes.c_int] * 3 + [P(ctypes.c_float)] * 2 + \
-                [P(d), d, ctypes.c_int, P(d), ctypes.c_int, d, ctypes.c_int] + \
-                [ctypes.c_int] * 4 + [P(d), P(d)]
+                [P(d), d, ctypes.c_int, P(d), P(d), ctypes.c_int, d, ctypes.c_int, P(d),
+                 ctypes.c_int] + [ctypes.c_int] * 4 + [P(d), P(d)]
             lib.oracle_search.restype = ctypes.c_int
             lib.oracle_hypotheses.argtypes = [ctypes.c_int] * 3 + [P(ctypes.c_float)] * 2 + \
-                [P(d), d, ctypes.c_int, P(d), ctypes.c_int, d, ctypes.c_int, ctypes.c_int,
-                 P(i32), P(i32), P(i32), P(d), P(d)]
+                [P(d), d, ctypes.c_int, P(d), P(d), ctypes.c_int, d, ctypes.c_int, P(d),
+                 ctypes.c_int, ctypes.c_int, P(i32), P(i32), P(i32), P(d), P(d)]
             lib.oracle_hypotheses.restype = ctypes.c_int
             lib.oracle_threads.restype = ctypes.c_int
             _lib = lib
@@ -87,12 +90,12 @@ def resolve_t_ref(times, t_ref):
     return float(t_ref)
 
 
-def offset(v: float, dt: float):
-    """Integer anchor floor(v*dt + 1/2) and phase v*dt - anchor (FP64)."""
+def offset(v: float, dt: float, th: float = 0.0):
+    """Integer anchor floor(v*dt + th + 1/2) and phase v*dt + th - anchor (FP64)."""
     lib = _load()
     i = ctypes.c_int32()
     f = ctypes.c_double()
-    lib.oracle_offset(float(v), float(dt), ctypes.byref(i), ctypes.byref(f))
+    lib.oracle_offset(float(v), float(dt), float(th), ctypes.byref(i), ctypes.byref(f))
     return int(i.value), float(f.value)
 
 
@@ -103,19 +106,60 @@ def profile(kind: int, sigma_px: float, stamp: int, f: float) -> np.ndarray:
     return g
 
 
-def offsets(times, t_ref, vel):
-    """(iy, ix, fy, fx), each [J][T], for velocities vel [J][2] = (vx, vy)."""
+def table_size(stamp: int, q: int) -> int:
+    """Side of a tabulated PRF grid: offsets -(h+1) .. h+1 in steps of 1/q."""
+    return (stamp + 1) * q + 1
+
+
+def _table(prf_table, stamp, q):
+    if prf_table is None:
+        return None
+    t = np.ascontiguousarray(prf_table, dtype=np.float64)
+    n = table_size(stamp, q)
+    if t.shape != (n, n):
+        raise ValueError("PRF table must be %dx%d for stamp %d, q %d" % (n, n, stamp, q))
+    return t
+
+
+def _opt(a, ctype):
+    return None if a is None else _ptr(a, ctype)
+
+
+def weights(kind: int, sigma_px: float, stamp: int, fy: float, fx: float, prf_table=None,
+            prf_q: int = 0) -> np.ndarray:
+    """Stamp weights W[a+h][b+h] at phase (fy, fx): the separable Gaussian
+    product, or the tabulated PRF read at (a - fy, b - fx)."""
+    t = _table(prf_table, stamp, prf_q)
+    w = np.zeros((stamp, stamp), dtype=np.float64)
+    _load().oracle_weights(int(kind), float(sigma_px), int(stamp), _opt(t, ctypes.c_double),
+                           int(prf_q), float(fy), float(fx), _ptr(w, ctypes.c_double))
+    return w
+
+
+def _jitter(jitter, T):
+    if jitter is None:
+        return None
+    j = np.ascontiguousarray(jitter, dtype=np.float64)
+    if j.shape != (T, 2):
+        raise ValueError("jitter must be [T][2] = (theta_x, theta_y)")
+    return j
+
+
+def offsets(times, t_ref, vel, jitter=None):
+    """(iy, ix, fy, fx), each [J][T], for velocities vel [J][2] = (vx, vy) and
+    optional per-frame jitter [T][2] = (theta_x, theta_y)."""
     times = np.ascontiguousarray(times, dtype=np.float64)
     vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 2)
     T, J = times.shape[0], vel.shape[0]
+    jit = _jitter(jitter, T)
     iy = np.zeros((J, T), np.int32)
     ix = np.zeros((J, T), np.int32)
     fy = np.zeros((J, T), np.float64)
     fx = np.zeros((J, T), np.float64)
     _load().oracle_offsets(T, _ptr(times, ctypes.c_double), resolve_t_ref(times, t_ref), J,
-                           _ptr(vel, ctypes.c_double), _ptr(iy, ctypes.c_int32),
-                           _ptr(ix, ctypes.c_int32), _ptr(fy, ctypes.c_double),
-                           _ptr(fx, ctypes.c_double))
+                           _ptr(vel, ctypes.c_double), _opt(jit, ctypes.c_double),
+                           _ptr(iy, ctypes.c_int32), _ptr(ix, ctypes.c_int32),
+                           _ptr(fy, ctypes.c_double), _ptr(fx, ctypes.c_double))
     return iy, ix, fy, fx
 
 
@@ -129,12 +173,13 @@ def _finish(nu, lam):
 
 
 def search(R, sigma, times, t_ref, vel, prf_kind=PRF_SAMPLED, sigma_px=0.7, stamp=5,
-           region=None):
+           region=None, prf_table=None, prf_q=0, jitter=None):
     """Full FP64 search.  R [T][H][W] float32, sigma [H][W] float32.
 
     region = (y_lo, y_hi, x_lo, x_hi) restricts the start pixels (the frames
-    are always read whole).  Returns dict of [J][ny][nx] float64 maps
-    nu, lam, snr, flux.
+    are always read whole).  prf_kind PRF_TABLE reads prf_table
+    [(stamp+1)q+1]^2 at oversampling prf_q; jitter is [T][2] or None.
+    Returns dict of [J][ny][nx] float64 maps nu, lam, snr, flux.
     """
     R = np.ascontiguousarray(R, dtype=np.float32)
     sigma = np.ascontiguousarray(sigma, dtype=np.float32)
@@ -142,14 +187,17 @@ def search(R, sigma, times, t_ref, vel, prf_kind=PRF_SAMPLED, sigma_px=0.7, stam
     vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 2)
     T, H, W = R.shape
     J = vel.shape[0]
+    tab = _table(prf_table, stamp, prf_q)
+    jit = _jitter(jitter, T)
     y_lo, y_hi, x_lo, x_hi = region if region is not None else (0, H, 0, W)
     ny, nx = y_hi - y_lo, x_hi - x_lo
     nu = np.zeros((J, ny, nx), np.float64)
     lam = np.zeros((J, ny, nx), np.float64)
     rc = _load().oracle_search(H, W, T, _ptr(R, ctypes.c_float), _ptr(sigma, ctypes.c_float),
                                _ptr(times, ctypes.c_double), resolve_t_ref(times, t_ref), J,
-                               _ptr(vel, ctypes.c_double), int(prf_kind), float(sigma_px),
-                               int(stamp), y_lo, y_hi, x_lo, x_hi,
+                               _ptr(vel, ctypes.c_double), _opt(jit, ctypes.c_double),
+                               int(prf_kind), float(sigma_px), int(stamp),
+                               _opt(tab, ctypes.c_double), int(prf_q), y_lo, y_hi, x_lo, x_hi,
                                _ptr(nu, ctypes.c_double), _ptr(lam, ctypes.c_double))
     if rc != 0:
         raise ValueError("oracle_search rejected its arguments")
@@ -158,7 +206,7 @@ def search(R, sigma, times, t_ref, vel, prf_kind=PRF_SAMPLED, sigma_px=0.7, stam
 
 
 def hypotheses(R, sigma, times, t_ref, vel, hj, hy, hx, prf_kind=PRF_SAMPLED,
-               sigma_px=0.7, stamp=5):
+               sigma_px=0.7, stamp=5, prf_table=None, prf_q=0, jitter=None):
     """FP64 sums for an explicit list of hypotheses (j, y0, x0)."""
     R = np.ascontiguousarray(R, dtype=np.float32)
     sigma = np.ascontiguousarray(sigma, dtype=np.float32)
@@ -168,15 +216,19 @@ def hypotheses(R, sigma, times, t_ref, vel, hj, hy, hx, prf_kind=PRF_SAMPLED,
     hy = np.ascontiguousarray(hy, dtype=np.int32)
     hx = np.ascontiguousarray(hx, dtype=np.int32)
     T, H, W = R.shape
+    tab = _table(prf_table, stamp, prf_q)
+    jit = _jitter(jitter, T)
     n = hj.shape[0]
     nu = np.zeros(n, np.float64)
     lam = np.zeros(n, np.float64)
     rc = _load().oracle_hypotheses(H, W, T, _ptr(R, ctypes.c_float), _ptr(sigma, ctypes.c_float),
                                    _ptr(times, ctypes.c_double), resolve_t_ref(times, t_ref),
-                                   vel.shape[0], _ptr(vel, ctypes.c_double), int(prf_kind),
-                                   float(sigma_px), int(stamp), n, _ptr(hj, ctypes.c_int32),
-                                   _ptr(hy, ctypes.c_int32), _ptr(hx, ctypes.c_int32),
-                                   _ptr(nu, ctypes.c_double), _ptr(lam, ctypes.c_double))
+                                   vel.shape[0], _ptr(vel, ctypes.c_double),
+                                   _opt(jit, ctypes.c_double), int(prf_kind), float(sigma_px),
+                                   int(stamp), _opt(tab, ctypes.c_double), int(prf_q), n,
+                                   _ptr(hj, ctypes.c_int32), _ptr(hy, ctypes.c_int32),
+                                   _ptr(hx, ctypes.c_int32), _ptr(nu, ctypes.c_double),
+                                   _ptr(lam, ctypes.c_double))
     if rc != 0:
         raise ValueError("oracle_hypotheses rejected its arguments")
     snr, flux = _finish(nu, lam)

@@ -119,11 +119,14 @@ def _prf_1d(offsets: np.ndarray, sigma_px: float, integrated: bool) -> np.ndarra
 
 
 def render_sources(shape, times, t_ref, sources, sigma_px: float = 0.7, stamp: int = 5,
-                   integrated: bool = False):
+                   integrated: bool = False, jitter=None, psf=None):
     """Forward model of moving point sources: per frame, each source deposits
-    amp * PRF on the stamp of pixels nearest its position, the stamp's response
-    normalised to unit sum.  Returns (k, y, x, value) arrays of the non-zero
-    contributions that fall on the image (float64 values)."""
+    amp * PRF on the stamp of pixels nearest its position (moved by the
+    frame's pointing jitter [T][2] = (theta_x, theta_y) if given).  With the
+    Gaussian PRF the stamp's response is normalised to unit sum; a `psf`
+    object (see TabulatedPSF) gives each pixel's share as is.  Returns
+    (k, y, x, value) arrays of the contributions that fall on the image
+    (float64 values)."""
     T, H, W = shape
     h = stamp // 2
     ks, ys, xs, vs = [], [], [], []
@@ -133,12 +136,17 @@ def render_sources(shape, times, t_ref, sources, sigma_px: float = 0.7, stamp: i
             dt = float(times[k]) - t_ref
             px = s.x + s.vx * dt
             py = s.y + s.vy * dt
+            if jitter is not None:
+                px += float(jitter[k][0])
+                py += float(jitter[k][1])
             cx = math.floor(px + 0.5)
             cy = math.floor(py + 0.5)
-            rx = _prf_1d(taps - (px - cx), sigma_px, integrated)
-            ry = _prf_1d(taps - (py - cy), sigma_px, integrated)
-            rx = rx / rx.sum()
-            ry = ry / ry.sum()
+            if psf is not None:
+                share = psf.pixel_share(taps[:, None] - (py - cy), taps[None, :] - (px - cx))
+            else:
+                rx = _prf_1d(taps - (px - cx), sigma_px, integrated)
+                ry = _prf_1d(taps - (py - cy), sigma_px, integrated)
+                share = np.outer(ry / ry.sum(), rx / rx.sum())
             for a in range(stamp):
                 Y = cy - h + a
                 if Y < 0 or Y >= H:
@@ -150,7 +158,7 @@ def render_sources(shape, times, t_ref, sources, sigma_px: float = 0.7, stamp: i
                     ks.append(k)
                     ys.append(Y)
                     xs.append(X)
-                    vs.append(s.amp * ry[a] * rx[b])
+                    vs.append(s.amp * share[a, b])
     return (np.array(ks, np.int64), np.array(ys, np.int64), np.array(xs, np.int64),
             np.array(vs, np.float64))
 
@@ -189,6 +197,67 @@ def draw_sources(g: np.random.Generator, n: int, vel: np.ndarray, H: int, W: int
         if any((x - s.x) ** 2 + (y - s.y) ** 2 < min_sep ** 2 for s in out):
             continue
         out.append(Source(x, y, float(vx), float(vy), float(g.uniform(amp_lo, amp_hi)), j))
+    return out
+
+
+# ---------------------------------------------------------------- tabulated PRF and jitter
+
+class TabulatedPSF:
+    """A non-separable, slightly asymmetric point-spread function standing in
+    for the TESS PRF model files (not available here): an elliptical Gaussian
+    core, rotated off the pixel axes, plus a fainter displaced halo, both of
+    unit integral.  `pixel_share(dy, dx)` is the fraction of a point source's
+    flux that a pixel whose centre lies at offset (dy, dx) from the source
+    records (midpoint rule over sub x sub points per pixel).  With the default
+    shape 49% of the flux lands in the peak pixel of a centred source and 87%
+    in the 2 x 2 pixels around a source on a pixel corner (Sec. 2.1 quotes
+    about 50% and 90% for TESS)."""
+
+    def __init__(self, core=(0.5, 0.38), angle_deg=35.0, halo_frac=0.15, halo_sigma=1.1,
+                 halo_offset=(0.15, -0.1), sub=12):
+        self.sa, self.sb = core
+        self.th = math.radians(angle_deg)
+        self.hf, self.hs = halo_frac, halo_sigma
+        self.hoy, self.hox = halo_offset
+        self.sub = sub
+
+    def density(self, y, x):
+        c, s = math.cos(self.th), math.sin(self.th)
+        u = c * x + s * y
+        v = -s * x + c * y
+        core = np.exp(-0.5 * ((u / self.sa) ** 2 + (v / self.sb) ** 2)) / (2 * math.pi * self.sa * self.sb)
+        yy, xx = y - self.hoy, x - self.hox
+        halo = np.exp(-0.5 * (xx * xx + yy * yy) / self.hs ** 2) / (2 * math.pi * self.hs ** 2)
+        return (1.0 - self.hf) * core + self.hf * halo
+
+    def pixel_share(self, dy, dx):
+        dy, dx = np.broadcast_arrays(np.asarray(dy, np.float64), np.asarray(dx, np.float64))
+        n = self.sub
+        o = (np.arange(n) + 0.5) / n - 0.5
+        y = dy[..., None, None] + o[:, None]
+        x = dx[..., None, None] + o[None, :]
+        return self.density(y, x).mean(axis=(-1, -2))
+
+    def table(self, stamp: int, q: int) -> np.ndarray:
+        """pixel_share on the grid -(h+1) .. h+1 in steps of 1/q, [n][n], rows
+        along y: the layout of a tabulated PRF."""
+        h = stamp // 2
+        u = -(h + 1) + np.arange((stamp + 1) * q + 1, dtype=np.float64) / q
+        return self.pixel_share(u[:, None], u[None, :])
+
+
+def jitter_series(g: np.random.Generator, T: int, amp: float = 0.15) -> np.ndarray:
+    """Per-frame pointing jitter [T][2] = (theta_x, theta_y) in pixels: a
+    smoothed random walk per axis, scaled so its largest excursion is `amp`
+    (Sec. 2.2 shows up to +-0.15 px in Sector 5), referenced to frame 0."""
+    out = np.zeros((T, 2))
+    for ax in range(2):
+        w = np.cumsum(g.standard_normal(T))
+        k = max(1, T // 50)
+        w = np.convolve(w, np.ones(k) / k, mode="same") + 0.3 * g.standard_normal(T)
+        w = w - w[0]
+        m = np.abs(w).max()
+        out[:, ax] = w * (amp / m) if m > 0 else 0.0
     return out
 
 

@@ -8,8 +8,8 @@ import math
 import numpy as np
 
 
-def anchor_phase(v, dt):
-    d = v * dt
+def anchor_phase(v, dt, th=0.0):
+    d = v * dt + th
     a = math.floor(d + 0.5)
     return a, d - a
 
@@ -28,19 +28,36 @@ def profile(f, sigma_px, stamp, integrated=False):
     return [x / s for x in g]
 
 
-def dense_filter(j, y0, x0, T, H, W, times, t_ref, vel, sigma_px, stamp, integrated=False):
+def table_read(tab, q, stamp, uy, ux):
+    """Tabulated PRF at offset (uy, ux): grid u = -(h+1) + i/q, read between
+    the four surrounding grid points with weights linear in each axis."""
+    r = stamp // 2 + 1
+    py, px = (uy + r) * q, (ux + r) * q
+    i, m = int(math.floor(py)), int(math.floor(px))
+    sy, sx = py - i, px - m
+    return ((1 - sy) * (1 - sx) * tab[i][m] + (1 - sy) * sx * tab[i][m + 1]
+            + sy * (1 - sx) * tab[i + 1][m] + sy * sx * tab[i + 1][m + 1])
+
+
+def dense_filter(j, y0, x0, T, H, W, times, t_ref, vel, sigma_px, stamp, integrated=False,
+                 table=None, q=0, jitter=None):
     F = np.zeros((T, H, W))
     h = stamp // 2
     for k in range(T):
-        ax, fx = anchor_phase(vel[j][0], times[k] - t_ref)
-        ay, fy = anchor_phase(vel[j][1], times[k] - t_ref)
-        gx = profile(fx, sigma_px, stamp, integrated)
-        gy = profile(fy, sigma_px, stamp, integrated)
+        thx, thy = (jitter[k][0], jitter[k][1]) if jitter is not None else (0.0, 0.0)
+        ax, fx = anchor_phase(vel[j][0], times[k] - t_ref, thx)
+        ay, fy = anchor_phase(vel[j][1], times[k] - t_ref, thy)
+        if table is None:
+            gx = profile(fx, sigma_px, stamp, integrated)
+            gy = profile(fy, sigma_px, stamp, integrated)
         for a in range(-h, h + 1):
             for b in range(-h, h + 1):
                 Y, X = y0 + ay + a, x0 + ax + b
                 if 0 <= Y < H and 0 <= X < W:
-                    F[k, Y, X] = gy[a + h] * gx[b + h]
+                    if table is None:
+                        F[k, Y, X] = gy[a + h] * gx[b + h]
+                    else:
+                        F[k, Y, X] = table_read(table, q, stamp, a - fy, b - fx)
     return F
 
 
@@ -50,7 +67,8 @@ def ivar_map(sigma):
     return np.where(ok, 1.0 / np.where(ok, s, 1.0) ** 2, 0.0)
 
 
-def search(R, sigma, times, t_ref, vel, sigma_px=0.7, stamp=5, integrated=False):
+def search(R, sigma, times, t_ref, vel, sigma_px=0.7, stamp=5, integrated=False, table=None,
+           q=0, jitter=None):
     T, H, W = R.shape
     J = len(vel)
     iv = ivar_map(sigma)
@@ -61,7 +79,7 @@ def search(R, sigma, times, t_ref, vel, sigma_px=0.7, stamp=5, integrated=False)
         for y0 in range(H):
             for x0 in range(W):
                 F = dense_filter(j, y0, x0, T, H, W, times, t_ref, vel, sigma_px, stamp,
-                                 integrated)
+                                 integrated, table, q, jitter)
                 nu[j, y0, x0] = float(np.sum(F * D))
                 lam[j, y0, x0] = float(np.sum(F * F * iv[None]))
     return nu, lam

@@ -397,3 +397,36 @@ def test_detections_order_and_threshold(oracle_mod):
     assert [(t[4], t[5]) for t in d] == [(0, 1), (1, 0), (1, 2), (0, 2)]
     assert d[0][2] == 15.0 and d[2][2] == 4.0
     assert len(oracle_mod.detections(sig, best, bj, flux, 3.0, 2)) == 2
+
+
+# ------------------------------------------------------------------ shift-stack vs matched filter
+
+def _closed_form_ratio(f, sigma_px=0.7, stamp=5):
+    """Noise-free SNR(matched filter) / SNR(shift-stack) for a source on the
+    filter's own track, sigma = 1, one frame at phase f per axis:
+    SNR_mf = A sqrt(sum W^2), SNR_ss = A W(anchor) (1-pixel filter of weight 1)."""
+    taps = np.arange(stamp) - stamp // 2
+    g = np.exp(-0.5 * ((taps - f) / sigma_px) ** 2)
+    g /= g.sum()
+    w2 = (g ** 2).sum() ** 2
+    return math.sqrt(w2) / g[stamp // 2] ** 2
+
+
+@pytest.mark.parametrize("f,expect", [(0.0, 1.26), (0.49, 2.0)])
+def test_shift_stack_is_the_one_pixel_filter(oracle_mod, f, expect):
+    """A 1x1 stamp is the shift-stack filter (one weight of 1 at the pixel
+    nearest the track per frame, Sec. 3.2); on a noise-free source its SNR is
+    below the full PRF filter's by the closed-form ratio."""
+    T, H, W = 1, 15, 15
+    v = f / (1.0 / 48.0) if f else 0.0
+    times = np.array([2000.0 + 1.0 / 48.0]) if f else np.array([2000.0])
+    t_ref = 2000.0
+    src = [synth.Source(7.0, 7.0, v, v, 1.0)]
+    R = synth.add_sources(np.zeros((T, H, W)), times, t_ref, src).astype(np.float32)
+    sig = np.ones((H, W), np.float32)
+    vel = np.array([[v, v]])
+    mf = oracle_mod.hypotheses(R, sig, times, t_ref, vel, [0], [7], [7], stamp=5)["snr"][0]
+    ss = oracle_mod.hypotheses(R, sig, times, t_ref, vel, [0], [7], [7], stamp=1)["snr"][0]
+    ratio = mf / ss
+    assert abs(ratio - _closed_form_ratio(f)) < 1e-6 * ratio
+    assert abs(ratio - expect) < 0.05
