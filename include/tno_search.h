@@ -58,6 +58,13 @@ extern "C" {
 /* PRF model (Sec. 2: PRF; Sec. 3.2: filter = trajectory line (x) PRF). */
 #define TNO_PRF_GAUSS_SAMPLED 0     /* exp(-(b-f)^2 / (2 s^2)) at pixel centres */
 #define TNO_PRF_GAUSS_INTEGRATED 1  /* Gaussian integrated over each pixel */
+#define TNO_PRF_TABLE 2             /* caller's tabulated PRF (Sec. 2.1: the share of a point
+                                       source's flux each pixel records), not separable in
+                                       general; read at the sub-pixel phase by bilinear
+                                       interpolation (see tno_prf) */
+
+/* Largest oversampling of a tabulated PRF. */
+#define TNO_MAX_TABLE_Q 64
 
 /* Side of the square quantisation tiles of the reduced-precision stacks. */
 #define TNO_QTILE 64
@@ -88,10 +95,23 @@ typedef struct {
                                     tuning (one line per arch and shape class), or NULL */
 } tno_config;
 
+/* Stamp weights of frame k (Sec. 3.2): with phase (f_y, f_x) in [-1/2, 1/2)
+ * of the trail position, pixel (a, b) of the stamp, a, b = -h..h, weighs
+ *   Gaussian kinds:  g(a - f_y) g(b - f_x), each 1-D profile scaled to unit sum;
+ *   TNO_PRF_TABLE:   P(a - f_y, b - f_x), as given (no renormalisation), where
+ *                    P is `table` [n][n], n = (S+1)*table_q + 1, row-major with
+ *                    rows along y, sampling offsets u = -(h+1) + i/table_q
+ *                    (i = 0..n-1) from the source, read between samples by
+ *                    bilinear interpolation (FP64).  Values are used as given;
+ *                    non-finite entries make non-finite scores. */
 typedef struct {
     int32_t kind;                /* TNO_PRF_* */
     int32_t stamp;               /* odd side S of the S x S stamp, 1..TNO_MAX_STAMP */
-    double sigma_px;             /* Gaussian sigma in pixels, > 0 */
+    double sigma_px;             /* Gaussian sigma in pixels, > 0 (ignored for TNO_PRF_TABLE) */
+    const double *table;         /* TNO_PRF_TABLE: [n][n] samples as above (copied at submit;
+                                    host memory unless TNO_REQ_DEVICE_PTRS); else ignored */
+    int32_t table_q;             /* TNO_PRF_TABLE: samples per pixel, 1..TNO_MAX_TABLE_Q */
+    int32_t reserved;            /* must be 0 */
 } tno_prf;
 
 typedef struct {
@@ -110,6 +130,10 @@ typedef struct {
     int32_t n_traj;              /* J >= 1 */
     int32_t top_k;               /* candidates wanted, 0..TNO_MAX_TOPK */
     const double *velocities;    /* [J][2] = (vx, vy) in pixels per unit of `times` */
+    const double *jitter;        /* [T][2] = (theta_x, theta_y): pointing jitter of each frame
+                                    in pixels (Sec. 2.2, 3.1), added to the trail position of
+                                    every trajectory in that frame: v*(t_k - t_ref) + theta_k;
+                                    finite, |theta| <= 256; NULL: none */
     int32_t sig_box;             /* 0: no significance map; else the odd side of the square
                                     window (e.g. 255) over which the local standard deviation
                                     of the best-score map is taken (Sec. 3.3) */

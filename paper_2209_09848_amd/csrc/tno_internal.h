@@ -8,30 +8,34 @@
 
 namespace tno {
 
-// Search tile shapes.  A lane owns CPL adjacent columns x SEARCH_RPL rows; a
-// wave spans 64*CPL columns; a block stacks NWAVE waves vertically.  Variant
-// 0 is the default; the others are autotuning candidates (stamp 5 only).
-constexpr int SEARCH_RPL = 8;
+// Search tile shapes.  A lane owns CPL adjacent columns x RPL rows; a wave
+// spans 64*CPL columns; a block stacks NWAVE waves vertically.  Variant 0 is
+// the default; the others are autotuning candidates (stamp 5 only).
 struct SearchVariant {
-    int nwave, cpl;
+    int nwave, cpl, rpl;
     const char *name;
 };
 inline constexpr SearchVariant SEARCH_VARIANTS[] = {
-    {4, 2, "w4c2"}, {8, 2, "w8c2"}, {2, 2, "w2c2"}, {4, 1, "w4c1"}, {8, 1, "w8c1"}, {4, 4, "w4c4"},
+    {4, 2, 8, "w4c2"}, {8, 2, 8, "w8c2"}, {2, 2, 8, "w2c2"}, {4, 1, 8, "w4c1"},
+    {8, 1, 8, "w8c1"}, {4, 4, 8, "w4c4"}, {2, 2, 16, "w2c2r16"}, {4, 2, 16, "w4c2r16"},
 };
-constexpr int N_SEARCH_VARIANTS = 6;
+constexpr int N_SEARCH_VARIANTS = 8;
 constexpr int SEARCH_MAX_TX = 256;
 constexpr int SEARCH_MAX_TY = 64;
 __host__ __device__ constexpr int search_tx(int v) { return 64 * SEARCH_VARIANTS[v].cpl; }
-__host__ __device__ constexpr int search_ty(int v) { return SEARCH_RPL * SEARCH_VARIANTS[v].nwave; }
+__host__ __device__ constexpr int search_ty(int v) { return SEARCH_VARIANTS[v].rpl * SEARCH_VARIANTS[v].nwave; }
 // Normaliser tile: 64 columns (1 per lane) x 32 rows (8 per lane, 4 waves).
 constexpr int LAMBDA_TX = 64;
 constexpr int LAMBDA_TY = 32;
 // Frames summed in FP32 before each FP64 accumulation of the numerator.
 constexpr int FRAME_CHUNK = 8;
 
-// Dwords per offset/weight table entry: iy, ix, gy[S], gx[S], padded to 16 bytes.
-__host__ __device__ constexpr int table_stride(int S) { return (2 + 2 * S + 3) & ~3; }
+// Dwords per offset/weight table entry, padded to 16 bytes: iy, ix and the
+// FP32 weights, gy[S], gx[S] for a separable (Gaussian) PRF or W[S][S]
+// (row-major) for a tabulated one.  The FP64 weights of the trail kernel
+// use the same order without the shifts: 2S or S*S doubles per entry.
+__host__ __device__ constexpr int table_stride(int S, bool sep) { return (2 + (sep ? 2 * S : S * S) + 3) & ~3; }
+__host__ __device__ constexpr int table64_stride(int S, bool sep) { return sep ? 2 * S : S * S; }
 
 // Per-trajectory layout of the collapsed trail kernel K_j (column runs).
 struct TrailInfo {
@@ -56,7 +60,7 @@ struct TopkState {
 
 struct SearchArgs {
     const float4 *Z4;        // padded inverse-variance-weighted stack [T][Hp][Wp4] float4
-    const int32_t *tab32;    // [J][T][table_stride(S)]
+    const int32_t *tab32;    // [J][T][table_stride(S, sep)]
     const double *lam;       // [J][H][W]
     float *snr;              // [J][H][W]
     float *flux;             // [J][H][W]
@@ -85,14 +89,26 @@ hipError_t launch_ivar(hipStream_t st, int HW, const float *sigma, float *ivar32
 hipError_t launch_prep_z(hipStream_t st, int dtype, const void *R, const float *scales,
                          const float *ivar32, float4 *Z4, int T, int H, int W, int Hp, int Wp4,
                          int Pt, int Pl);
+// The PRF of one request: kind, stamp, Gaussian sigma or the tabulated grid.
+struct PrfSpec {
+    int kind;
+    int S;
+    double sigma_px;
+    const double *table;     // device [(S+1)q+1]^2 for TNO_PRF_TABLE, else unused
+    int q;
+};
+__host__ __device__ constexpr bool prf_separable(int kind) { return kind != TNO_PRF_TABLE; }
+
 hipError_t launch_table(hipStream_t st, int J, int T, const double *times, double t_ref,
-                        const double *vel, int kind, double sigma_px, int S, int32_t *tab32,
-                        double *tab64);
-hipError_t launch_trail(hipStream_t st, int J, int T, int S, int H, const int32_t *tab32,
+                        const double *vel, const double *jitter, const PrfSpec &prf,
+                        int32_t *tab32, double *tab64);
+hipError_t launch_trail(hipStream_t st, int J, int T, int S, bool sep, const int32_t *tab32,
                         const double *tab64, const TrailInfo *info, int2 *colmeta,
                         double *kvals, int32_t *err);
 hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a);
-hipError_t launch_search(hipStream_t st, int S, int variant, const SearchArgs &a);
+// Variants 0..N_SEARCH_VARIANTS-1 for the separable stamp of side 5; variant 0
+// for every other (stamp, separability).
+hipError_t launch_search(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a);
 hipError_t launch_trajmax(hipStream_t st, int J, int ntiles, int W, int HW,
                           const uint64_t *tile_keys, const float *snr, const float *flux,
                           void *traj_max_out);
@@ -101,11 +117,13 @@ hipError_t launch_best(hipStream_t st, int J, int HW, const float *snr, float *b
 hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int64_t N, int HW,
                        int W, int k, TopkState *state, uint32_t *chunk_cnt, int64_t n_chunks,
                        uint64_t *cand, void *topk_out);
+// Doubles in each of the two block-sum buffers of the significance pass.
+int64_t significance_block_values(int H, int W);
 hipError_t launch_significance(hipStream_t st, int H, int W, int box, float thr, int k,
                                const float *best_snr, const int32_t *best_traj, const float *flux,
-                               double *r1, double *r2, float *sig, TopkState *state,
-                               uint32_t *chunk_cnt, int64_t n_chunks, uint64_t *cand,
-                               tno_detection *det, int32_t *counts);
+                               double *r1, double *r2, double *b1, double *b2, float *sig,
+                               TopkState *state, uint32_t *chunk_cnt, int64_t n_chunks,
+                               uint64_t *cand, tno_detection *det, int32_t *counts);
 hipError_t launch_quantize(hipStream_t st, int dtype, const float *R, int T, int H, int W,
                            void *codes, float *scales);
 

@@ -4,11 +4,14 @@
 // Pipeline of one request (all on one HIP stream):
 //   k_ivar      ivar = 1/sigma^2 (FP64, also rounded to FP32); 0 for masked pixels
 //   k_prep_z    Z = decode(R) * ivar into a zero-padded FP32 stack (float4 rows)
-//   k_table     per (trajectory, frame): FP64 anchor/phase and PRF profiles
+//   k_table     per (trajectory, frame): FP64 anchor/phase (pointing jitter
+//               included) and the stamp weights (Gaussian profiles or the
+//               tabulated PRF read at the phase)
 //   k_trail     per trajectory: collapsed trail kernel K_j(q) = sum_k W_jk^2 at q (FP64)
 //   k_lambda    Lam_j = ivar (x) K_j, a sparse FP64 correlation
 //   k_search    nu_j = sum_k W_jk (x) Z_k at the frame's shift; LDS-staged window,
-//               separable PRF, FP32 frame chunks into FP64 totals; epilogue
+//               separable (2S taps) or general (S*S taps) stamp, FP32 frame
+//               chunks into FP64 totals; epilogue
 //               SNR = nu/sqrt(Lam), flux = nu/Lam, per-tile maximum key
 //   k_trajmax / k_best / top-k   the reductions of Sec. 3.2-3.3
 #include <hip/hip_runtime.h>
@@ -130,6 +133,9 @@ __device__ __forceinline__ float load_residual(const void *R, const float *scale
 }
 
 // One thread per float4 group of the padded stack; grid (groups/256, Hp, T).
+// A group holds image columns 4g..4g+3 in the order (4g, 4g+2, 4g+1, 4g+3):
+// even columns first, so the search can stage a row's even and odd columns
+// into separate halves with whole 8-byte stores.
 template <int DT>
 __global__ void k_prep_z(const void *__restrict__ R, const float *__restrict__ scales,
                          const float *__restrict__ ivar32, float4 *__restrict__ Z4, int H, int W,
@@ -176,7 +182,7 @@ __global__ void k_prep_z(const void *__restrict__ R, const float *__restrict__ s
                 }
             }
         }
-        Z4[((size_t)k * Hp + yp) * Wp4 + g] = make_float4(r[0] * iv.x, r[1] * iv.y, r[2] * iv.z, r[3] * iv.w);
+        Z4[((size_t)k * Hp + yp) * Wp4 + g] = make_float4(r[0] * iv.x, r[2] * iv.z, r[1] * iv.y, r[3] * iv.w);
         return;
     }
 #pragma unroll
@@ -189,7 +195,7 @@ __global__ void k_prep_z(const void *__restrict__ R, const float *__restrict__ s
             v[e] = r * ivar32[p];
         }
     }
-    Z4[((size_t)k * Hp + yp) * Wp4 + g] = make_float4(v[0], v[1], v[2], v[3]);
+    Z4[((size_t)k * Hp + yp) * Wp4 + g] = make_float4(v[0], v[2], v[1], v[3]);
 }
 
 hipError_t launch_prep_z(hipStream_t st, int dtype, const void *R, const float *scales,
@@ -248,60 +254,97 @@ __device__ void prf_profile(int kind, double sp, int S, double f, double *g)
         g[b] = g[b] / sum;
 }
 
-// One thread per (trajectory j, frame k): anchor i = floor(v*dt + 1/2) and
-// phase f = v*dt - i per axis in FP64 without fused multiply-add (the anchor
-// must flip exactly where the definition flips), then both profiles.
+// Tabulated PRF at offset (uy, ux) by bilinear interpolation of the grid
+// tab[n][n], n = (S+1)q+1, samples at u = -(h+1) + i/q.  |u| <= h + 1/2 keeps
+// the cell inside the grid.
+__device__ double prf_table_value(const double *__restrict__ tab, int S, int q, double uy,
+                                  double ux)
+{
+#pragma clang fp contract(off)
+    const int n = (S + 1) * q + 1;
+    const double r = (double)(S / 2 + 1);
+    const double gy = (uy + r) * (double)q, gx = (ux + r) * (double)q;
+    const double cy = floor(gy), cx = floor(gx);
+    const double ty = gy - cy, tx = gx - cx;
+    const int i = min(max((int)cy, 0), n - 2), m = min(max((int)cx, 0), n - 2);
+    const double *r0 = tab + (size_t)i * n;
+    const double *r1 = r0 + n;
+    const double top = (1.0 - tx) * r0[m] + tx * r0[m + 1];
+    const double bot = (1.0 - tx) * r1[m] + tx * r1[m + 1];
+    return (1.0 - ty) * top + ty * bot;
+}
+
+// One thread per (trajectory j, frame k): displacement D = v*dt + theta_k,
+// anchor i = floor(D + 1/2) and phase f = D - i per axis in FP64 without
+// fused multiply-add (the anchor must flip exactly where the definition
+// flips), then the stamp weights: both Gaussian profiles, or the S x S
+// tabulated weights P(a - f_y, b - f_x).
 __global__ void k_table(int J, int T, const double *__restrict__ times, double t_ref,
-                        const double *__restrict__ vel, int kind, double sp, int S,
-                        int32_t *__restrict__ tab32, double *__restrict__ tab64)
+                        const double *__restrict__ vel, const double *__restrict__ jitter,
+                        PrfSpec prf, int32_t *__restrict__ tab32, double *__restrict__ tab64)
 {
 #pragma clang fp contract(off)
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= J * T)
         return;
+    const int S = prf.S;
     int j = e / T, k = e - j * T;
     double dt = times[k] - t_ref;
-    double dx = vel[2 * j + 0] * dt;
-    double dy = vel[2 * j + 1] * dt;
+    const double thx = jitter ? jitter[2 * k + 0] : 0.0;
+    const double thy = jitter ? jitter[2 * k + 1] : 0.0;
+    double dx = vel[2 * j + 0] * dt + thx;
+    double dy = vel[2 * j + 1] * dt + thy;
     double ax = floor(dx + 0.5), ay = floor(dy + 0.5);
     double fx = dx - ax, fy = dy - ay;
-    double gy[TNO_MAX_STAMP], gx[TNO_MAX_STAMP];
-    prf_profile(kind, sp, S, fy, gy);
-    prf_profile(kind, sp, S, fx, gx);
-    const int TS = table_stride(S);
+    const bool sep = prf_separable(prf.kind);
+    const int TS = table_stride(S, sep);
+    const int T64 = table64_stride(S, sep);
     int32_t *t = tab32 + (size_t)e * TS;
+    double *t64 = tab64 + (size_t)e * T64;
     t[0] = (int32_t)ay;
     t[1] = (int32_t)ax;
-    for (int s = 0; s < S; ++s) {
-        t[2 + s] = __float_as_int((float)gy[s]);
-        t[2 + S + s] = __float_as_int((float)gx[s]);
+    if (sep) {
+        double gy[TNO_MAX_STAMP], gx[TNO_MAX_STAMP];
+        prf_profile(prf.kind, prf.sigma_px, S, fy, gy);
+        prf_profile(prf.kind, prf.sigma_px, S, fx, gx);
+        for (int s = 0; s < S; ++s) {
+            t[2 + s] = __float_as_int((float)gy[s]);
+            t[2 + S + s] = __float_as_int((float)gx[s]);
+            t64[s] = gy[s];
+            t64[S + s] = gx[s];
+        }
+    } else {
+        const int h = S / 2;
+        for (int a = 0; a < S; ++a)
+            for (int b = 0; b < S; ++b) {
+                const double w = prf_table_value(prf.table, S, prf.q, (double)(a - h) - fy,
+                                                 (double)(b - h) - fx);
+                t[2 + a * S + b] = __float_as_int((float)w);
+                t64[a * S + b] = w;
+            }
     }
-    for (int s = 2 + 2 * S; s < TS; ++s)
+    for (int s = 2 + T64; s < TS; ++s)
         t[s] = 0;
-    double *t64 = tab64 + (size_t)e * 2 * S;
-    for (int s = 0; s < S; ++s) {
-        t64[s] = gy[s];
-        t64[S + s] = gx[s];
-    }
 }
 
 hipError_t launch_table(hipStream_t st, int J, int T, const double *times, double t_ref,
-                        const double *vel, int kind, double sigma_px, int S, int32_t *tab32,
-                        double *tab64)
+                        const double *vel, const double *jitter, const PrfSpec &prf,
+                        int32_t *tab32, double *tab64)
 {
     int n = J * T;
     hipLaunchKernelGGL(k_table, dim3((n + 127) / 128), dim3(128), 0, st, J, T, times, t_ref, vel,
-                       kind, sigma_px, S, tab32, tab64);
+                       jitter, prf, tab32, tab64);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ k_trail (FP64)
 
 // One block per trajectory, one thread per column offset qx of the trail box.
-// K_j(qy, qx) = sum_k gx_k(qx - ix_k)^2 gy_k(qy - iy_k)^2 over the frames whose
+// K_j(qy, qx) = sum_k W_jk(qy - iy_k, qx - ix_k)^2 over the frames whose
 // stamp covers (qy, qx); each column is one contiguous run of rows, summed
-// frame by frame in frame order (deterministic).
-__global__ void k_trail(int T, int S, const int32_t *__restrict__ tab32,
+// frame by frame in frame order (deterministic).  W is gy*gx for a separable
+// PRF, the tabulated weight otherwise.
+__global__ void k_trail(int T, int S, int sep, const int32_t *__restrict__ tab32,
                         const double *__restrict__ tab64, const TrailInfo *__restrict__ info,
                         int2 *__restrict__ colmeta, double *__restrict__ kvals,
                         int32_t *__restrict__ err)
@@ -309,9 +352,10 @@ __global__ void k_trail(int T, int S, const int32_t *__restrict__ tab32,
     const int j = blockIdx.x;
     const TrailInfo ti = info[j];
     const int h = S / 2;
-    const int TS = table_stride(S);
+    const int TS = table_stride(S, sep);
+    const int T64 = table64_stride(S, sep);
     const int32_t *tj = tab32 + (size_t)j * T * TS;
-    const double *t64 = tab64 + (size_t)j * T * 2 * S;
+    const double *t64 = tab64 + (size_t)j * T * T64;
     for (int c = threadIdx.x; c < ti.ncols; c += blockDim.x) {
         const int qx = ti.qx0 + c;
         int lo = INT_MAX, hi = INT_MIN;
@@ -343,26 +387,36 @@ __global__ void k_trail(int T, int S, const int32_t *__restrict__ tab32,
             if (dxo < -h || dxo > h)
                 continue;
             int iy = tj[(size_t)k * TS + 0];
-            double wx = t64[(size_t)k * 2 * S + S + dxo + h];
-            double wx2 = wx * wx;
-            for (int a = 0; a < S; ++a) {
-                int r = iy - h + a - lo;
-                if (r < 0 || r >= len)
-                    continue;
-                double wy = t64[(size_t)k * 2 * S + a];
-                kv[r] += wx2 * (wy * wy);
+            const double *wk = t64 + (size_t)k * T64;
+            if (sep) {
+                double wx = wk[S + dxo + h];
+                double wx2 = wx * wx;
+                for (int a = 0; a < S; ++a) {
+                    int r = iy - h + a - lo;
+                    if (r < 0 || r >= len)
+                        continue;
+                    double wy = wk[a];
+                    kv[r] += wx2 * (wy * wy);
+                }
+            } else {
+                for (int a = 0; a < S; ++a) {
+                    int r = iy - h + a - lo;
+                    if (r < 0 || r >= len)
+                        continue;
+                    double w = wk[a * S + dxo + h];
+                    kv[r] += w * w;
+                }
             }
         }
     }
 }
 
-hipError_t launch_trail(hipStream_t st, int J, int T, int S, int H, const int32_t *tab32,
+hipError_t launch_trail(hipStream_t st, int J, int T, int S, bool sep, const int32_t *tab32,
                         const double *tab64, const TrailInfo *info, int2 *colmeta,
                         double *kvals, int32_t *err)
 {
-    (void)H;
-    hipLaunchKernelGGL(k_trail, dim3(J), dim3(256), 0, st, T, S, tab32, tab64, info, colmeta,
-                       kvals, err);
+    hipLaunchKernelGGL(k_trail, dim3(J), dim3(256), 0, st, T, S, (int)sep, tab32, tab64, info,
+                       colmeta, kvals, err);
     return hipGetLastError();
 }
 
@@ -461,11 +515,10 @@ hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a)
 // pass of S taps per window row streamed into a vertical pass of S taps.  The
 // table entry (shift, PRF taps) is wave-uniform (scalar loads).  Frame
 // partials accumulate in FP32 over FRAME_CHUNK frames, then into FP64.
-template <int S, int NWAVE, int CPL>
+template <int S, int NWAVE, int CPL, int RPL, bool SEP>
 __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
 {
     constexpr int h = S / 2;
-    constexpr int RPL = SEARCH_RPL;
     constexpr int NT = 64 * NWAVE;
     constexpr int TX = 64 * CPL, TY = RPL * NWAVE;
     constexpr int WY = TY + S - 1;
@@ -473,9 +526,10 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
     constexpr int LS = NG * 4;
     constexpr int NWIN = WY * NG;
     constexpr int NLD = (NWIN + NT - 1) / NT;
-    constexpr int TS = table_stride(S);
+    constexpr int TS = table_stride(S, SEP);
+    constexpr int NW = table64_stride(S, SEP);   // FP32 weights per table entry
     constexpr int NV = CPL + S - 1;
-    __shared__ float4 win4[2][NWIN];
+    __shared__ __align__(16) float win[2][NWIN * 4];
 
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.n_items)
@@ -538,11 +592,25 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
         }
         return ox - (ag << 2);
     };
+    // LDS window, de-interleaved: the even columns of all WY rows, then the
+    // odd columns (rows of LH floats each).  A staged group arrives as (even,
+    // even, odd, odd), so each half takes one 8-byte store.  With an even
+    // number of columns per lane, a lane's run of window columns splits into
+    // one run in each half whose order does not depend on the parity of the
+    // frame's sub-float4 offset: one code path serves every frame.  The short
+    // rows keep four rows of a half within one LDS instruction's offset range.
+    constexpr bool SPLIT = CPL % 2 == 0;
+    constexpr int LH = LS / 2;
+    constexpr int HALF = WY * LH;
     auto store = [&](int buf, const float4 (&pre)[NLD]) {
 #pragma unroll
         for (int it = 0; it < NLD; ++it)
-            if (it < NLD - 1 || last_ok)
-                win4[buf][tid + NT * it] = pre[it];
+            if (it < NLD - 1 || last_ok) {
+                const int idx = tid + NT * it;
+                const int r = idx / NG, g = idx - r * NG;
+                reinterpret_cast<float2 *>(&win[buf][r * LH])[g] = make_float2(pre[it].x, pre[it].y);
+                reinterpret_cast<float2 *>(&win[buf][HALF + r * LH])[g] = make_float2(pre[it].z, pre[it].w);
+            }
     };
 
     float part[RPL][CPL];
@@ -559,93 +627,105 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
     int d_cur = fetch(0, pre);
     store(0, pre);
     __syncthreads();
-    for (int k = 0; k < a.nframes; ++k) {
-        const int buf = k & 1;
-        // the last iteration re-fetches frame T-1 into the idle buffer: no
-        // branch around the prefetch, so its store stays behind the arithmetic
-        const int d_next = fetch(min(k + 1, a.nframes - 1), pre);
+    for (int k0 = 0; k0 < a.nframes; k0 += FRAME_CHUNK) {
+        const int k1 = min(k0 + FRAME_CHUNK, a.nframes);
+        for (int k = k0; k < k1; ++k) {
+            const int buf = k & 1;
+            // the last iteration re-fetches frame T-1 into the idle buffer: no
+            // branch around the prefetch, so its store stays behind the arithmetic
+            const int d_next = fetch(min(k + 1, a.nframes - 1), pre);
 
-        const cint32_t *e = tabj + (size_t)k * TS;
-        float gy[S], gx[S];
+            const cint32_t *e = tabj + (size_t)k * TS;
+            float wt[NW];     // gy[S], gx[S] (separable) or W[S][S]
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            gy[s] = __int_as_float(e[2 + s]);
-            gx[s] = __int_as_float(e[2 + S + s]);
-        }
-        // One frame of the separable stamp.  ODD is the parity of the lane's
-        // first window column: with an even number of columns per lane it is
-        // the parity of d, and reading 8-byte pairs from the even column at or
-        // before it lets every LDS read use an immediate offset (no address
-        // arithmetic per row).
-        auto frame = [&](auto odd_tag) {
-            constexpr int ODD = decltype(odd_tag)::value;
-            constexpr int NP = (NV + ODD + 1) / 2;
-            const float *wbase = reinterpret_cast<const float *>(win4[buf]) + (wv * RPL) * LS + CPL * lane;
+            for (int s = 0; s < NW; ++s)
+                wt[s] = __int_as_float(e[2 + s]);
+            // this wave's first window row in the even half
+            const float *wrow = win[buf] + (wv * RPL) * LH;
+            // SPLIT: first column s = d + CPL*lane has the parity of d; values
+            // v[0], v[2], .. come from the half of that parity starting at s/2,
+            // v[1], v[3], .. from the other half starting at (s+1)/2
+            // (odd CPL: column s + t sits at half (s+t)&1, index (s+t)>>1)
+            const int par = d_cur & 1;
+            const float *pa = wrow + par * HALF + (d_cur >> 1) + (CPL / 2) * lane;
+            const float *pb = wrow + (1 - par) * HALF + ((d_cur + 1) >> 1) + (CPL / 2) * lane;
+            const float *pt[SPLIT ? 1 : NV];
+            if constexpr (!SPLIT) {
+                const int s0 = d_cur + CPL * lane;
+#pragma unroll
+                for (int t = 0; t < NV; ++t)
+                    pt[t] = wrow + ((s0 + t) & 1) * HALF + ((s0 + t) >> 1);
+            }
 #pragma unroll
             for (int rr = 0; rr < RPL + S - 1; ++rr) {
                 float v[NV];
-                if constexpr (CPL % 2 == 0) {
-                    const float2 *p2 = reinterpret_cast<const float2 *>(wbase + (d_cur - ODD) + rr * LS);
-                    float2 pr[NP];
 #pragma unroll
-                    for (int q = 0; q < NP; ++q)
-                        pr[q] = p2[q];
-                    if constexpr (ODD)   // keep the partly used end pairs 8-byte loads
-                        asm volatile("" : : "v"(pr[0]), "v"(pr[NP - 1]));
+                for (int t = 0; t < NV; ++t) {
+                    if constexpr (SPLIT)
+                        v[t] = (t & 1) ? pb[rr * LH + (t >> 1)] : pa[rr * LH + (t >> 1)];
+                    else
+                        v[t] = pt[t][rr * LH];
+                }
+                if constexpr (SEP) {
+                    // horizontal pass of the row, streamed into the vertical pass
+                    float hs[CPL];
 #pragma unroll
-                    for (int t = 0; t < NV; ++t)
-                        v[t] = ((t + ODD) & 1) ? pr[(t + ODD) >> 1].y : pr[(t + ODD) >> 1].x;
+                    for (int c = 0; c < CPL; ++c) {
+                        float sum = wt[S] * v[c];
+#pragma unroll
+                        for (int b = 1; b < S; ++b)
+                            sum = fmaf(wt[S + b], v[c + b], sum);
+                        hs[c] = sum;
+                    }
+#pragma unroll
+                    for (int aa = 0; aa < S; ++aa) {
+                        const int o = rr - aa;
+                        if (o >= 0 && o < RPL) {
+#pragma unroll
+                            for (int c = 0; c < CPL; ++c)
+                                part[o][c] = fmaf(wt[aa], hs[c], part[o][c]);
+                        }
+                    }
                 } else {
+                    // general stamp: window row rr is stamp row aa of output row rr - aa
 #pragma unroll
-                    for (int t = 0; t < NV; ++t)
-                        v[t] = wbase[d_cur + rr * LS + t];
-                }
-                float hs[CPL];
+                    for (int aa = 0; aa < S; ++aa) {
+                        const int o = rr - aa;
+                        if (o >= 0 && o < RPL) {
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    float sum = gx[0] * v[c];
+                            for (int c = 0; c < CPL; ++c) {
+                                float sum = part[o][c];
 #pragma unroll
-                    for (int b = 1; b < S; ++b)
-                        sum = fmaf(gx[b], v[c + b], sum);
-                    hs[c] = sum;
-                }
-#pragma unroll
-                for (int aa = 0; aa < S; ++aa) {
-                    const int o = rr - aa;
-                    if (o >= 0 && o < RPL) {
-#pragma unroll
-                        for (int c = 0; c < CPL; ++c)
-                            part[o][c] = fmaf(gy[aa], hs[c], part[o][c]);
+                                for (int b = 0; b < S; ++b)
+                                    sum = fmaf(wt[aa * S + b], v[c + b], sum);
+                                part[o][c] = sum;
+                            }
+                        }
                     }
                 }
             }
-        };
-        if (CPL % 2 == 0 && (d_cur & 1))
-            frame(std::integral_constant<int, 1>{});
-        else
-            frame(std::integral_constant<int, 0>{});
-        // keep the store (and its wait on the prefetch loads) after the
-        // arithmetic, so the loads' latency hides behind it: the empty
-        // volatile asm statements consume every accumulator, and the store
-        // (a side effect) is not moved above them
-#pragma unroll
-        for (int o = 0; o < RPL; ++o)
-#pragma unroll
-            for (int c = 0; c < CPL; ++c)
-                asm volatile("" : "+v"(part[o][c]));
-        __builtin_amdgcn_sched_barrier(0);
-        store(buf ^ 1, pre);
-        __syncthreads();
-        d_cur = d_next;
-        if ((k % FRAME_CHUNK) == FRAME_CHUNK - 1) {
+            // keep the store (and its wait on the prefetch loads) after the
+            // arithmetic, so the loads' latency hides behind it: the empty
+            // volatile asm statements consume every accumulator, and the store
+            // (a side effect) is not moved above them
 #pragma unroll
             for (int o = 0; o < RPL; ++o)
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    acc[o][c] += (double)part[o][c];
-                    part[o][c] = 0.0f;
-                }
+                for (int c = 0; c < CPL; ++c)
+                    asm volatile("" : "+v"(part[o][c]));
+            __builtin_amdgcn_sched_barrier(0);
+            store(buf ^ 1, pre);
+            __syncthreads();
+            d_cur = d_next;
         }
+        // frame chunk done: into the FP64 totals
+#pragma unroll
+        for (int o = 0; o < RPL; ++o)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                acc[o][c] += (double)part[o][c];
+                part[o][c] = 0.0f;
+            }
     }
 
     // epilogue: SNR and flux, and the tile's largest (SNR, -pixel) key
@@ -695,15 +775,16 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
     }
 }
 
-template <int S, int NWAVE, int CPL>
+template <int S, int NWAVE, int CPL, int RPL = 8, bool SEP = true>
 static void launch_search_t(hipStream_t st, const SearchArgs &a)
 {
-    hipLaunchKernelGGL((k_search<S, NWAVE, CPL>), dim3(xcd_grid(a.n_items)), dim3(64 * NWAVE), 0, st, a);
+    hipLaunchKernelGGL((k_search<S, NWAVE, CPL, RPL, SEP>), dim3(xcd_grid(a.n_items)),
+                       dim3(64 * NWAVE), 0, st, a);
 }
 
-hipError_t launch_search(hipStream_t st, int S, int variant, const SearchArgs &a)
+hipError_t launch_search(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a)
 {
-    if (S == 5) {
+    if (S == 5 && sep) {
         switch (variant) {
         case 0: launch_search_t<5, 4, 2>(st, a); break;
         case 1: launch_search_t<5, 8, 2>(st, a); break;
@@ -711,21 +792,37 @@ hipError_t launch_search(hipStream_t st, int S, int variant, const SearchArgs &a
         case 3: launch_search_t<5, 4, 1>(st, a); break;
         case 4: launch_search_t<5, 8, 1>(st, a); break;
         case 5: launch_search_t<5, 4, 4>(st, a); break;
+        case 6: launch_search_t<5, 2, 2, 16>(st, a); break;
+        case 7: launch_search_t<5, 4, 2, 16>(st, a); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
     if (variant != 0)
         return hipErrorInvalidValue;
-    switch (S) {
-    case 1: launch_search_t<1, 4, 2>(st, a); break;
-    case 3: launch_search_t<3, 4, 2>(st, a); break;
-    case 7: launch_search_t<7, 4, 2>(st, a); break;
-    case 9: launch_search_t<9, 4, 2>(st, a); break;
-    case 11: launch_search_t<11, 4, 2>(st, a); break;
-    case 13: launch_search_t<13, 4, 2>(st, a); break;
-    case 15: launch_search_t<15, 4, 2>(st, a); break;
-    default: return hipErrorInvalidValue;
+    if (sep) {
+        switch (S) {
+        case 1: launch_search_t<1, 4, 2>(st, a); break;
+        case 3: launch_search_t<3, 4, 2>(st, a); break;
+        case 7: launch_search_t<7, 4, 2>(st, a); break;
+        case 9: launch_search_t<9, 4, 2>(st, a); break;
+        case 11: launch_search_t<11, 4, 2>(st, a); break;
+        case 13: launch_search_t<13, 4, 2>(st, a); break;
+        case 15: launch_search_t<15, 4, 2>(st, a); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (S) {
+        case 1: launch_search_t<1, 4, 2, 8, false>(st, a); break;
+        case 3: launch_search_t<3, 4, 2, 8, false>(st, a); break;
+        case 5: launch_search_t<5, 4, 2, 8, false>(st, a); break;
+        case 7: launch_search_t<7, 4, 2, 8, false>(st, a); break;
+        case 9: launch_search_t<9, 4, 2, 8, false>(st, a); break;
+        case 11: launch_search_t<11, 4, 2, 8, false>(st, a); break;
+        case 13: launch_search_t<13, 4, 2, 8, false>(st, a); break;
+        case 15: launch_search_t<15, 4, 2, 8, false>(st, a); break;
+        default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }
@@ -1045,83 +1142,131 @@ hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int6
 // The paper expresses each pixel's best score in units of the standard
 // deviation of the scores in the box x box square centred on it.  Windows are
 // clipped at the image edges; the std is the population std of the scores
-// inside, from FP64 sliding sums of s and s^2 along rows, then columns; a
+// inside, from FP64 window sums of s and s^2 along rows, then columns; a
 // variance below 1e-12 of the window's mean square counts as 0.
 
-constexpr int BOX_SEG = 64;   // outputs per thread of a sliding pass
+constexpr int BOX_BLK = 16;   // aligned block of the window sums
 
-__global__ void k_box_rows(int H, int W, int hb, const float *__restrict__ s,
-                           double *__restrict__ r1, double *__restrict__ r2)
+// Window sums never slide: a window's sum is its loose ends plus the sums of
+// the aligned blocks of BOX_BLK values it covers, so it depends only on the
+// values inside the window (a constant window gives the exact square of its
+// mean, and a one-pixel window a variance of exactly 0).
+
+// Block sums along each row of the best map: (sum v, sum v^2) per block.
+__global__ void k_box_rblk(int H, int W, const float *__restrict__ s, double *__restrict__ b1,
+                           double *__restrict__ b2)
 {
-    const int nseg = (W + BOX_SEG - 1) / BOX_SEG;
+    const int nb = (W + BOX_BLK - 1) / BOX_BLK;
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= H * nseg)
+    if (gid >= H * nb)
         return;
-    const int y = gid / nseg, x0 = (gid - y * nseg) * BOX_SEG;
+    const int y = gid / nb, b = gid - y * nb;
     const float *row = s + (size_t)y * W;
     double a1 = 0.0, a2 = 0.0;
-    for (int x = max(0, x0 - hb); x <= min(W - 1, x0 + hb); ++x) {
-        double v = row[x];
+    for (int x = b * BOX_BLK; x < min(W, (b + 1) * BOX_BLK); ++x) {
+        const double v = row[x];
         a1 += v;
         a2 += v * v;
     }
-    const int x1 = min(W, x0 + BOX_SEG);
-    for (int x = x0; x < x1; ++x) {
-        if (x > x0) {
-            if (x + hb < W) {
-                double v = row[x + hb];
-                a1 += v;
-                a2 += v * v;
-            }
-            if (x - hb - 1 >= 0) {
-                double v = row[x - hb - 1];
-                a1 -= v;
-                a2 -= v * v;
-            }
-        }
-        r1[(size_t)y * W + x] = a1;
-        r2[(size_t)y * W + x] = a2;
-    }
+    b1[gid] = a1;
+    b2[gid] = a2;
 }
 
-// Column pass: box sums, counts, std and significance = best / std (0 if std == 0).
-__global__ void k_box_cols(int H, int W, int hb, const double *__restrict__ r1,
-                           const double *__restrict__ r2, const float *__restrict__ s,
-                           float *__restrict__ sig)
+// Row window sums over [x-hb, x+hb] clipped to the row.
+__global__ void k_box_rows(int H, int W, int hb, const float *__restrict__ s,
+                           const double *__restrict__ b1, const double *__restrict__ b2,
+                           double *__restrict__ r1, double *__restrict__ r2)
 {
-    const int nseg = (H + BOX_SEG - 1) / BOX_SEG;
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= W * nseg)
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)H * W)
         return;
-    const int x = gid % W, y0 = (gid / W) * BOX_SEG;   // adjacent threads: adjacent columns
-    const double nx = (double)(min(W - 1, x + hb) - max(0, x - hb) + 1);
+    const int y = (int)(gid / W), x = (int)(gid - (int64_t)y * W);
+    const int nb = (W + BOX_BLK - 1) / BOX_BLK;
+    const float *row = s + (size_t)y * W;
+    const int lo = max(0, x - hb), hi = min(W - 1, x + hb);
+    const int bl = (lo + BOX_BLK - 1) / BOX_BLK, bh = (hi + 1) / BOX_BLK;   // whole blocks [bl, bh)
     double a1 = 0.0, a2 = 0.0;
-    for (int y = max(0, y0 - hb); y <= min(H - 1, y0 + hb); ++y) {
+    auto one = [&](int xx) {
+        const double v = row[xx];
+        a1 += v;
+        a2 += v * v;
+    };
+    if (bl < bh) {
+        for (int xx = lo; xx < bl * BOX_BLK; ++xx)
+            one(xx);
+        for (int b = bl; b < bh; ++b) {
+            a1 += b1[(size_t)y * nb + b];
+            a2 += b2[(size_t)y * nb + b];
+        }
+        for (int xx = bh * BOX_BLK; xx <= hi; ++xx)
+            one(xx);
+    } else {
+        for (int xx = lo; xx <= hi; ++xx)
+            one(xx);
+    }
+    r1[gid] = a1;
+    r2[gid] = a2;
+}
+
+// Block sums down each column of the row window sums.
+__global__ void k_box_cblk(int H, int W, const double *__restrict__ r1,
+                           const double *__restrict__ r2, double *__restrict__ b1,
+                           double *__restrict__ b2)
+{
+    const int nb = (H + BOX_BLK - 1) / BOX_BLK;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)nb * W)
+        return;
+    const int b = (int)(gid / W), x = (int)(gid - (int64_t)b * W);   // adjacent threads: adjacent columns
+    double a1 = 0.0, a2 = 0.0;
+    for (int y = b * BOX_BLK; y < min(H, (b + 1) * BOX_BLK); ++y) {
         a1 += r1[(size_t)y * W + x];
         a2 += r2[(size_t)y * W + x];
     }
-    const int y1 = min(H, y0 + BOX_SEG);
-    for (int y = y0; y < y1; ++y) {
-        if (y > y0) {
-            if (y + hb < H) {
-                a1 += r1[(size_t)(y + hb) * W + x];
-                a2 += r2[(size_t)(y + hb) * W + x];
-            }
-            if (y - hb - 1 >= 0) {
-                a1 -= r1[(size_t)(y - hb - 1) * W + x];
-                a2 -= r2[(size_t)(y - hb - 1) * W + x];
-            }
+    b1[gid] = a1;
+    b2[gid] = a2;
+}
+
+// Column window sums, the clipped window's count, the population standard
+// deviation and significance = best / std (0 where std is 0).
+__global__ void k_box_cols(int H, int W, int hb, const double *__restrict__ r1,
+                           const double *__restrict__ r2, const double *__restrict__ b1,
+                           const double *__restrict__ b2, const float *__restrict__ s,
+                           float *__restrict__ sig)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)H * W)
+        return;
+    const int y = (int)(gid / W), x = (int)(gid - (int64_t)y * W);
+    const int lo = max(0, y - hb), hi = min(H - 1, y + hb);
+    const int bl = (lo + BOX_BLK - 1) / BOX_BLK, bh = (hi + 1) / BOX_BLK;
+    double a1 = 0.0, a2 = 0.0;
+    auto one = [&](int yy) {
+        a1 += r1[(size_t)yy * W + x];
+        a2 += r2[(size_t)yy * W + x];
+    };
+    if (bl < bh) {
+        for (int yy = lo; yy < bl * BOX_BLK; ++yy)
+            one(yy);
+        for (int b = bl; b < bh; ++b) {
+            a1 += b1[(size_t)b * W + x];
+            a2 += b2[(size_t)b * W + x];
         }
-        const double n = nx * (double)(min(H - 1, y + hb) - max(0, y - hb) + 1);
-        const double mean = a1 / n;
-        const double var = a2 / n - mean * mean;
-        // running sums leave a residue of order 1e-16 of the mean square
-        // where the window is constant: treat such a variance as 0
-        const double sd = var > 1e-12 * (a2 / n) ? sqrt(var) : 0.0;
-        const size_t p = (size_t)y * W + x;
-        float g = sd > 0.0 ? (float)((double)s[p] / sd) : 0.0f;
-        sig[p] = g + 0.0f;
+        for (int yy = bh * BOX_BLK; yy <= hi; ++yy)
+            one(yy);
+    } else {
+        for (int yy = lo; yy <= hi; ++yy)
+            one(yy);
     }
+    const double nx = (double)(min(W - 1, x + hb) - max(0, x - hb) + 1);
+    const double n = nx * (double)(hi - lo + 1);
+    const double mean = a1 / n;
+    const double var = a2 / n - mean * mean;
+    // rounding of the sums leaves a residue of order n * 1e-16 of the mean
+    // square where the window is constant: treat such a variance as 0
+    const double sd = var > 1e-12 * (a2 / n) ? sqrt(var) : 0.0;
+    float g = sd > 0.0 ? (float)((double)s[gid] / sd) : 0.0f;
+    sig[gid] = g + 0.0f;
 }
 
 __global__ void k_count_above(int64_t N, const float *__restrict__ sig, float thr, int32_t *count)
@@ -1170,17 +1315,27 @@ __global__ __launch_bounds__(1024) void k_detect_final(
         *n_out = n_keep;
 }
 
+int64_t significance_block_values(int H, int W)
+{
+    return std::max<int64_t>((int64_t)H * ((W + BOX_BLK - 1) / BOX_BLK),
+                             (int64_t)W * ((H + BOX_BLK - 1) / BOX_BLK));
+}
+
 hipError_t launch_significance(hipStream_t st, int H, int W, int box, float thr, int k,
                                const float *best_snr, const int32_t *best_traj, const float *flux,
-                               double *r1, double *r2, float *sig, TopkState *state,
-                               uint32_t *chunk_cnt, int64_t n_chunks, uint64_t *cand,
-                               tno_detection *det, int32_t *counts)
+                               double *r1, double *r2, double *b1, double *b2, float *sig,
+                               TopkState *state, uint32_t *chunk_cnt, int64_t n_chunks,
+                               uint64_t *cand, tno_detection *det, int32_t *counts)
 {
     const int hb = box / 2;
-    const int nr = H * ((W + BOX_SEG - 1) / BOX_SEG), nc = W * ((H + BOX_SEG - 1) / BOX_SEG);
-    hipLaunchKernelGGL(k_box_rows, dim3((nr + 255) / 256), dim3(256), 0, st, H, W, hb, best_snr, r1, r2);
-    hipLaunchKernelGGL(k_box_cols, dim3((nc + 255) / 256), dim3(256), 0, st, H, W, hb, r1, r2, best_snr, sig);
     const int64_t HW = (int64_t)H * W;
+    const int64_t nrb = (int64_t)H * ((W + BOX_BLK - 1) / BOX_BLK);
+    const int64_t ncb = (int64_t)W * ((H + BOX_BLK - 1) / BOX_BLK);
+    auto grid = [](int64_t n) { return dim3((unsigned)((n + 255) / 256)); };
+    hipLaunchKernelGGL(k_box_rblk, grid(nrb), dim3(256), 0, st, H, W, best_snr, b1, b2);
+    hipLaunchKernelGGL(k_box_rows, grid(HW), dim3(256), 0, st, H, W, hb, best_snr, b1, b2, r1, r2);
+    hipLaunchKernelGGL(k_box_cblk, grid(ncb), dim3(256), 0, st, H, W, r1, r2, b1, b2);
+    hipLaunchKernelGGL(k_box_cols, grid(HW), dim3(256), 0, st, H, W, hb, r1, r2, b1, b2, best_snr, sig);
     int blocks = (int)std::min<int64_t>((HW + 255) / 256, 4096);
     hipLaunchKernelGGL(k_count_above, dim3(blocks), dim3(256), 0, st, HW, sig, thr, counts);
     if (k > 0) {

@@ -74,6 +74,9 @@ size_t elem_bytes(int dtype)
 struct Plan {
     int H = 0, W = 0, T = 0, J = 0, S = 0, h = 0, kind = 0, dtype = 0, k = 0;
     double sigma_px = 0, t_ref = 0;
+    bool sep = true;                  // separable (Gaussian) PRF; else the tabulated one
+    int table_q = 0, table_n = 0;     // tabulated PRF: samples per pixel, grid side
+    bool jitter = false;
     bool dev = false;
     int Pt = 0, Pb = 0, Pl = 0, Pr = 0, Hp = 0, Wp4 = 0;
     std::vector<tno::TrailInfo> trail;
@@ -94,7 +97,8 @@ struct Plan {
            o_iv64 = 0, o_tab32 = 0, o_tab64 = 0, o_trail = 0, o_colmeta = 0, o_kvals = 0,
            o_err = 0, o_lam = 0, o_snr = 0, o_flux = 0, o_tkeys = 0, o_tstate = 0, o_chunks = 0,
            o_cand = 0, o_tmax = 0, o_topk = 0, o_best = 0, o_bestj = 0, o_perm = 0, o_r1 = 0,
-           o_r2 = 0, o_sig = 0, o_det = 0, o_counts = 0, bytes = 0;
+           o_r2 = 0, o_b1 = 0, o_b2 = 0, o_sig = 0, o_det = 0, o_counts = 0, o_prf = 0, o_jit = 0,
+           bytes = 0;
 };
 
 bool finite(double v) { return std::isfinite(v); }
@@ -127,12 +131,21 @@ Fail check_shape(const tno_request *r, const tno_outputs *o)
         return fail(TNO_E_INVAL, "sigma must be non-NULL");
     if (!r->times || !r->velocities)
         return fail(TNO_E_INVAL, "times and velocities must be non-NULL");
-    if (r->prf.kind != TNO_PRF_GAUSS_SAMPLED && r->prf.kind != TNO_PRF_GAUSS_INTEGRATED)
+    if (r->prf.kind != TNO_PRF_GAUSS_SAMPLED && r->prf.kind != TNO_PRF_GAUSS_INTEGRATED &&
+        r->prf.kind != TNO_PRF_TABLE)
         return fail(TNO_E_INVAL, "unknown PRF kind %d", r->prf.kind);
     if (r->prf.stamp < 1 || r->prf.stamp > TNO_MAX_STAMP || (r->prf.stamp % 2) == 0)
         return fail(TNO_E_INVAL, "stamp must be odd and in 1..%d", TNO_MAX_STAMP);
-    if (!(r->prf.sigma_px > 0.0) || !finite(r->prf.sigma_px))
+    if (r->prf.reserved != 0)
+        return fail(TNO_E_INVAL, "prf.reserved must be 0");
+    if (r->prf.kind == TNO_PRF_TABLE) {
+        if (!r->prf.table)
+            return fail(TNO_E_INVAL, "TNO_PRF_TABLE needs prf.table");
+        if (r->prf.table_q < 1 || r->prf.table_q > TNO_MAX_TABLE_Q)
+            return fail(TNO_E_INVAL, "prf.table_q must be in 1..%d", TNO_MAX_TABLE_Q);
+    } else if (!(r->prf.sigma_px > 0.0) || !finite(r->prf.sigma_px)) {
         return fail(TNO_E_INVAL, "prf.sigma_px must be finite and > 0");
+    }
     if (r->top_k < 0 || r->top_k > TNO_MAX_TOPK)
         return fail(TNO_E_INVAL, "top_k must be in 0..%d", TNO_MAX_TOPK);
     if (r->top_k > 0 && !o->topk)
@@ -174,9 +187,9 @@ void set_search_shape(Plan &p, int v, int tblock)
     p.tblock = std::max(1, std::min(tblock, p.J));
 }
 
-// Build the plan from host copies of times and velocities.
+// Build the plan from host copies of times, velocities and jitter (NULL: none).
 Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
-               const double *vel, Plan &p)
+               const double *vel, const double *jit, Plan &p)
 {
     Fail f = check_shape(r, o);
     if (f.code)
@@ -189,6 +202,27 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     p.h = p.S / 2;
     p.kind = r->prf.kind;
     p.sigma_px = r->prf.sigma_px;
+    p.sep = tno::prf_separable(p.kind);
+    p.table_q = p.sep ? 0 : r->prf.table_q;
+    p.table_n = p.sep ? 0 : (p.S + 1) * p.table_q + 1;
+    p.jitter = jit != nullptr;
+    // jitter extremes per axis (0 when absent)
+    double jxmin = 0, jxmax = 0, jymin = 0, jymax = 0;
+    if (jit) {
+        for (int k = 0; k < r->n_frames; ++k) {
+            const double tx = jit[2 * k], ty = jit[2 * k + 1];
+            if (!finite(tx) || !finite(ty) || std::fabs(tx) > 256.0 || std::fabs(ty) > 256.0)
+                return fail(TNO_E_INVAL, "jitter[%d] must be finite with |theta| <= 256", k);
+            if (k == 0) {
+                jxmin = jxmax = tx;
+                jymin = jymax = ty;
+            }
+            jxmin = std::min(jxmin, tx);
+            jxmax = std::max(jxmax, tx);
+            jymin = std::min(jymin, ty);
+            jymax = std::max(jymax, ty);
+        }
+    }
     p.dtype = r->dtype;
     p.dev = (r->flags & TNO_REQ_DEVICE_PTRS) != 0;
     for (int k = 0; k < p.T; ++k)
@@ -203,8 +237,9 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     }
     if (!finite(dtmin) || !finite(dtmax))
         return fail(TNO_E_INVAL, "time baseline overflows");
-    // Shift bounds per trajectory: floor(v*dt + 1/2) is monotone in dt, so the
-    // extremes sit at the extreme times; one pixel of margin each side.
+    // Shift bounds per trajectory: v*dt is monotone in dt, so its extremes sit
+    // at the extreme times; the jitter adds its own extremes; one pixel of
+    // margin each side covers the rounding of the sums.
     int gymin = 0, gymax = 0, gxmin = 0, gxmax = 0;
     const int H = p.H, W = p.W, h = p.h, S = p.S;
     p.trail.resize(p.J);
@@ -217,8 +252,10 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
         for (double d : e)
             if (!(std::fabs(d) < 1.0e9))
                 return fail(TNO_E_INVAL, "trajectory %d moves more than 1e9 px", j);
-        double x1 = std::floor(e[0] + 0.5), x2 = std::floor(e[1] + 0.5);
-        double y1 = std::floor(e[2] + 0.5), y2 = std::floor(e[3] + 0.5);
+        double x1 = std::floor(std::min(e[0], e[1]) + jxmin + 0.5);
+        double x2 = std::floor(std::max(e[0], e[1]) + jxmax + 0.5);
+        double y1 = std::floor(std::min(e[2], e[3]) + jymin + 0.5);
+        double y2 = std::floor(std::max(e[2], e[3]) + jymax + 0.5);
         int xlo = (int)std::min(x1, x2) - 1, xhi = (int)std::max(x1, x2) + 1;
         int ylo = (int)std::min(y1, y2) - 1, yhi = (int)std::max(y1, y2) + 1;
         gxmin = std::min(gxmin, xlo);
@@ -234,7 +271,11 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
         int nrows = std::max(0, ti.qy_hi - ti.qy_lo + 1);
         int cap = nrows;
         if (vx != 0.0) {
-            double c = std::ceil((double)S * (1.0 + std::fabs(vy) / std::fabs(vx))) + 3.0;
+            // frames whose stamp covers one column have |v_x dt + theta_x - qx| <= h + 1/2:
+            // a time span of (S + jitter range in x) / |vx|, over which the row
+            // anchor moves by |vy| times that plus the jitter range in y
+            double c = std::ceil((double)S + ((double)S + (jxmax - jxmin)) * std::fabs(vy) / std::fabs(vx) +
+                                 (jymax - jymin)) + 3.0;
             if (c < (double)cap)
                 cap = (int)c;
         }
@@ -314,12 +355,16 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     if (!p.dev) {
         p.o_times = take(T * 8);
         p.o_vel = take(J * 16);
+        if (p.jitter)
+            p.o_jit = take(T * 16);
+        if (!p.sep)
+            p.o_prf = take((size_t)p.table_n * p.table_n * 8);
     }
     p.o_Z = take(T * (size_t)p.Hp * p.Wp4 * 16);
     p.o_iv32 = take(HW * 4);
     p.o_iv64 = take(HW * 8);
-    p.o_tab32 = take(J * T * tno::table_stride(S) * 4);
-    p.o_tab64 = take(J * T * 2 * S * 8);
+    p.o_tab32 = take(J * T * tno::table_stride(S, p.sep) * 4);
+    p.o_tab64 = take(J * T * tno::table64_stride(S, p.sep) * 8);
     p.o_trail = take(J * sizeof(tno::TrailInfo));
     p.o_colmeta = take((size_t)p.n_colmeta * 8);
     p.o_kvals = take((size_t)p.n_kvals * 8);
@@ -342,6 +387,8 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     if (p.box > 0) {
         p.o_r1 = take(HW * 8);
         p.o_r2 = take(HW * 8);
+        p.o_b1 = take((size_t)tno::significance_block_values(H, W) * 8);
+        p.o_b2 = take((size_t)tno::significance_block_values(H, W) * 8);
         p.o_sig = take(HW * 4);
         p.o_det = take((size_t)TNO_MAX_DETECTIONS * sizeof(tno_detection));
     }
@@ -530,6 +577,8 @@ struct Inputs {
     const float *sigma;
     const double *times;
     const double *vel;
+    const double *jit;       // NULL: no jitter
+    const double *prf_tab;   // tabulated PRF grid, or NULL
 };
 
 Inputs inputs_of(const Request *q, const tno_request *r)
@@ -553,6 +602,8 @@ Inputs inputs_of(const Request *q, const tno_request *r)
     }
     in.times = p.dev ? r->times : at<double>(A, p.o_times);
     in.vel = p.dev ? r->velocities : at<double>(A, p.o_vel);
+    in.jit = !p.jitter ? nullptr : p.dev ? r->jitter : at<double>(A, p.o_jit);
+    in.prf_tab = p.sep ? nullptr : p.dev ? r->prf.table : at<double>(A, p.o_prf);
     return in;
 }
 
@@ -616,9 +667,10 @@ hipError_t enqueue_front(Request *q, const tno_request *r)
     TRY(tno::launch_prep_z(st, p.dtype, in.R, in.scales, at<float>(A, p.o_iv32), at<float4>(A, p.o_Z),
                            p.T, p.H, p.W, p.Hp, p.Wp4, p.Pt, p.Pl));
     TRY(hipEventRecord(q->ev[1], st));
-    TRY(tno::launch_table(st, p.J, p.T, in.times, p.t_ref, in.vel, p.kind, p.sigma_px, p.S,
+    const tno::PrfSpec prf{p.kind, p.S, p.sigma_px, in.prf_tab, p.table_q};
+    TRY(tno::launch_table(st, p.J, p.T, in.times, p.t_ref, in.vel, in.jit, prf,
                           at<int32_t>(A, p.o_tab32), at<double>(A, p.o_tab64)));
-    TRY(tno::launch_trail(st, p.J, p.T, p.S, p.H, at<int32_t>(A, p.o_tab32), at<double>(A, p.o_tab64),
+    TRY(tno::launch_trail(st, p.J, p.T, p.S, p.sep, at<int32_t>(A, p.o_tab32), at<double>(A, p.o_tab64),
                           at<tno::TrailInfo>(A, p.o_trail), at<int2>(A, p.o_colmeta),
                           at<double>(A, p.o_kvals), at<int32_t>(A, p.o_err)));
     TRY(hipEventRecord(q->ev[2], st));
@@ -650,7 +702,7 @@ hipError_t enqueue_back(Request *q)
     const int HW = p.H * p.W;
     hipError_t e;
     const tno::SearchArgs sa = search_args(q, snr, flux, p.T);
-    TRY(tno::launch_search(st, p.S, p.variant, sa));
+    TRY(tno::launch_search(st, p.S, p.sep, p.variant, sa));
     TRY(hipEventRecord(q->ev[4], st));
     TRY(tno::launch_trajmax(st, p.J, p.ntiles, p.W, HW, sa.tile_keys, snr, flux, at<void>(A, p.o_tmax)));
     TRY(tno::launch_best(st, p.J, HW, snr, at<float>(A, p.o_best), at<int32_t>(A, p.o_bestj)));
@@ -662,7 +714,8 @@ hipError_t enqueue_back(Request *q)
     if (p.box > 0)
         TRY(tno::launch_significance(st, p.H, p.W, p.box, p.thr, p.kdet, at<float>(A, p.o_best),
                                      at<int32_t>(A, p.o_bestj), flux, at<double>(A, p.o_r1),
-                                     at<double>(A, p.o_r2), at<float>(A, p.o_sig),
+                                     at<double>(A, p.o_r2), at<double>(A, p.o_b1),
+                                     at<double>(A, p.o_b2), at<float>(A, p.o_sig),
                                      at<tno::TopkState>(A, p.o_tstate), at<uint32_t>(A, p.o_chunks),
                                      p.n_chunks, at<uint64_t>(A, p.o_cand),
                                      at<tno_detection>(A, p.o_det), at<int32_t>(A, p.o_counts)));
@@ -694,7 +747,8 @@ std::string shape_class(const Plan &p)
 {
     auto lg = [](int v) { int b = 0; while ((1 << b) < v) ++b; return b; };
     char buf[64];
-    snprintf(buf, sizeof buf, "S%d_H%d_W%d_J%d_T%d", p.S, lg(p.H), lg(p.W), lg(p.J), lg(p.T));
+    snprintf(buf, sizeof buf, "%s%d_H%d_W%d_J%d_T%d", p.sep ? "S" : "P", p.S, lg(p.H), lg(p.W), lg(p.J),
+             lg(p.T));
     return buf;
 }
 
@@ -709,7 +763,7 @@ hipError_t autotune(tno_search *h, Request *q)
         float ms;
     };
     std::vector<Cand> cands;
-    const int nv = p.S == 5 ? tno::N_SEARCH_VARIANTS : 1;
+    const int nv = (p.S == 5 && p.sep) ? tno::N_SEARCH_VARIANTS : 1;
     std::vector<int> tbs = {p.J};
     for (int tb : {64, 16})
         if (tb < p.J)
@@ -730,7 +784,7 @@ hipError_t autotune(tno_search *h, Request *q)
             if (rep == 1)
                 e = hipEventRecord(ev[2 * i], q->stream);
             if (e == hipSuccess)
-                e = tno::launch_search(q->stream, p.S, p.variant, sa);
+                e = tno::launch_search(q->stream, p.S, p.sep, p.variant, sa);
         }
         if (e == hipSuccess)
             e = hipEventRecord(ev[2 * i + 1], q->stream);
@@ -810,7 +864,7 @@ int tno_search_validate(const tno_request *req, const tno_outputs *out, char *ms
     Fail f = check_shape(req, out);
     if (f.code == TNO_OK && !(req->flags & TNO_REQ_DEVICE_PTRS)) {
         Plan p;
-        f = make_plan(req, out, req->times, req->velocities, p);
+        f = make_plan(req, out, req->times, req->velocities, req->jitter, p);
     }
     if (msg && len > 0)
         snprintf(msg, (size_t)len, "%s", f.msg);
@@ -822,7 +876,7 @@ uint64_t tno_search_footprint(const tno_request *req, const tno_outputs *out)
     if (!req || !out || (req->flags & TNO_REQ_DEVICE_PTRS))
         return 0;
     Plan p;
-    Fail f = make_plan(req, out, req->times, req->velocities, p);
+    Fail f = make_plan(req, out, req->times, req->velocities, req->jitter, p);
     if (f.code != TNO_OK)
         return 0;
     return (uint64_t)p.bytes + (req->stack_key ? p.stack_bytes : 0);
@@ -932,8 +986,8 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
         return TNO_E_INVAL;
     }
 
-    std::vector<double> times_h, vel_h;
-    const double *times = req->times, *vel = req->velocities;
+    std::vector<double> times_h, vel_h, jit_h;
+    const double *times = req->times, *vel = req->velocities, *jit = req->jitter;
     if (dev) {
         times_h.resize(req->n_frames);
         vel_h.resize((size_t)2 * req->n_traj);
@@ -942,13 +996,19 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
             return hip_fail(e, "reading times/velocities", nullptr, 0);
         times = times_h.data();
         vel = vel_h.data();
+        if (req->jitter) {
+            jit_h.resize((size_t)2 * req->n_frames);
+            if ((e = hipMemcpy(jit_h.data(), req->jitter, jit_h.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+                return hip_fail(e, "reading jitter", nullptr, 0);
+            jit = jit_h.data();
+        }
     }
     Request *q = new (std::nothrow) Request();
     if (!q) {
         set_last(fail(TNO_E_NOMEM, "out of host memory"));
         return TNO_E_NOMEM;
     }
-    f = make_plan(req, out, times, vel, q->plan);
+    f = make_plan(req, out, times, vel, jit, q->plan);
     if (f.code) {
         delete q;
         set_last(f);
@@ -1065,6 +1125,8 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
             {p.o_sigma, req->sigma, p.stack_in_arena ? HW * 4 : 0},
             {p.o_times, req->times, (size_t)p.T * 8},
             {p.o_vel, req->velocities, (size_t)p.J * 16},
+            {p.o_jit, req->jitter, p.jitter ? (size_t)p.T * 16 : 0},
+            {p.o_prf, req->prf.table, p.sep ? 0 : (size_t)p.table_n * p.table_n * 8},
         };
         for (auto &c : cps)
             if (c.bytes && (e = hipMemcpy(at<void>(A, c.off), c.src, c.bytes, hipMemcpyHostToDevice)) != hipSuccess) {
@@ -1075,7 +1137,7 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
     bool tune_now = false;
     {
         auto it = h->tuned.find(shape_class(q->plan));
-        if (it != h->tuned.end() && (q->plan.S == 5 || it->second.variant == 0))
+        if (it != h->tuned.end() && ((q->plan.S == 5 && q->plan.sep) || it->second.variant == 0))
             set_search_shape(q->plan, it->second.variant, it->second.tblock);
         else
             tune_now = h->autotune;

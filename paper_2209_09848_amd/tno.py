@@ -26,10 +26,11 @@ TNO_E_CANCELLED = -6
 TNO_E_INTERNAL = -7
 
 TNO_F32, TNO_BF16, TNO_F16, TNO_FP8_E4M3 = 0, 1, 2, 3
-TNO_PRF_GAUSS_SAMPLED, TNO_PRF_GAUSS_INTEGRATED = 0, 1
+TNO_PRF_GAUSS_SAMPLED, TNO_PRF_GAUSS_INTEGRATED, TNO_PRF_TABLE = 0, 1, 2
+TNO_MAX_TABLE_Q = 64
 TNO_CFG_GRAPHS = 1
 TNO_CFG_AUTOTUNE = 2
-SEARCH_VARIANTS = ("w4c2", "w8c2", "w2c2", "w4c1", "w8c1", "w4c4")
+SEARCH_VARIANTS = ("w4c2", "w8c2", "w2c2", "w4c1", "w8c1", "w4c4", "w2c2r16", "w4c2r16")
 TNO_REQ_DEVICE_PTRS = 1
 TNO_REQ_VALIDATE = 2
 TNO_MAX_TOPK = 1024
@@ -49,7 +50,8 @@ class tno_config(ctypes.Structure):
 
 
 class tno_prf(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("stamp", ctypes.c_int32), ("sigma_px", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int32), ("stamp", ctypes.c_int32), ("sigma_px", ctypes.c_double),
+                ("table", _vp), ("table_q", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class tno_request(ctypes.Structure):
@@ -57,7 +59,8 @@ class tno_request(ctypes.Structure):
                 ("n_frames", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("residuals", _vp), ("tile_scales", _vp), ("sigma", _vp), ("times", _vp),
                 ("t_ref", ctypes.c_double), ("prf", tno_prf), ("n_traj", ctypes.c_int32),
-                ("top_k", ctypes.c_int32), ("velocities", _vp), ("sig_box", ctypes.c_int32),
+                ("top_k", ctypes.c_int32), ("velocities", _vp), ("jitter", _vp),
+                ("sig_box", ctypes.c_int32),
                 ("sig_threshold", ctypes.c_float), ("stack_key", ctypes.c_uint64),
                 ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
@@ -193,9 +196,11 @@ def _ptr(t):
 def make_request(R, sigma, times, vel, *, t_ref=float("nan"), dtype="f32", scales=None,
                  sigma_px=0.7, stamp=5, prf_kind=TNO_PRF_GAUSS_SAMPLED, top_k=10,
                  stack_key=0, flags=TNO_REQ_DEVICE_PTRS, shape=None, sig_box=0,
-                 sig_threshold=5.0) -> tno_request:
+                 sig_threshold=5.0, prf_table=None, prf_q=0, jitter=None) -> tno_request:
     """A request over torch tensors on the GPU (device pointers).  R may be
-    None (search the stack resident under stack_key) with shape=(T, H, W)."""
+    None (search the stack resident under stack_key) with shape=(T, H, W).
+    prf_table (float64 [(stamp+1)q+1]^2, with prf_kind=TNO_PRF_TABLE and
+    prf_q=q) and jitter (float64 [T][2]) are tensors on the same device."""
     T, H, W = (int(s) for s in (R.shape if R is not None else shape))
     req = tno_request()
     req.height, req.width, req.n_frames = H, W, T
@@ -205,10 +210,11 @@ def make_request(R, sigma, times, vel, *, t_ref=float("nan"), dtype="f32", scale
     req.sigma = _ptr(sigma)
     req.times = _ptr(times)
     req.t_ref = float(t_ref) if t_ref is not None else float("nan")
-    req.prf = tno_prf(int(prf_kind), int(stamp), float(sigma_px))
+    req.prf = tno_prf(int(prf_kind), int(stamp), float(sigma_px), _ptr(prf_table), int(prf_q), 0)
     req.n_traj = int(vel.shape[0])
     req.top_k = int(top_k)
     req.velocities = _ptr(vel)
+    req.jitter = _ptr(jitter)
     req.sig_box = int(sig_box)
     req.sig_threshold = float(sig_threshold)
     req.stack_key = int(stack_key)
@@ -276,10 +282,10 @@ class Search:
         return res
 
 
-def shape_class(H, W, T, J, stamp=5) -> str:
+def shape_class(H, W, T, J, stamp=5, tabulated=False) -> str:
     """Tuning-table key the library uses for a request shape."""
     lg = lambda v: max(0, (int(v) - 1).bit_length())
-    return "S%d_H%d_W%d_J%d_T%d" % (stamp, lg(H), lg(W), lg(J), lg(T))
+    return "%s%d_H%d_W%d_J%d_T%d" % ("P" if tabulated else "S", stamp, lg(H), lg(W), lg(J), lg(T))
 
 
 def alloc_outputs(J, H, W, k, device="cuda", maps=True, detections=0):

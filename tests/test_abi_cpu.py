@@ -124,3 +124,33 @@ def test_create_without_gpu_reports_device_error():
     with pytest.raises(tno.TnoError) as e:
         tno.tno_search_create(cfg)
     assert e.value.code == tno.TNO_E_DEVICE
+
+
+def test_validate_tabulated_prf_and_jitter():
+    T = 5
+    tab = np.ones((6 * 4 + 1, 6 * 4 + 1))
+    jit = np.zeros((T, 2))
+    req, out, keep = _host_request(T=T)
+    req.prf = tno.tno_prf(tno.TNO_PRF_TABLE, 5, 0.0, tab.ctypes.data_as(ctypes.c_void_p), 4, 0)
+    req.jitter = jit.ctypes.data_as(ctypes.c_void_p)
+    rc, msg = tno.tno_search_validate(req, out)
+    assert rc == tno.TNO_OK, msg
+    f_tab = tno.tno_search_footprint(req, out)
+    req2, out2, keep2 = _host_request(T=T)
+    assert f_tab > tno.tno_search_footprint(req2, out2)      # S*S weights per table entry
+    for bad, needle in [((tno.TNO_PRF_TABLE, 5, 0.0, None, 4, 0), "prf.table"),
+                        ((tno.TNO_PRF_TABLE, 5, 0.0, tab.ctypes.data_as(ctypes.c_void_p), 0, 0), "table_q"),
+                        ((tno.TNO_PRF_TABLE, 5, 0.0, tab.ctypes.data_as(ctypes.c_void_p), 65, 0), "table_q"),
+                        ((tno.TNO_PRF_TABLE, 5, 0.0, tab.ctypes.data_as(ctypes.c_void_p), 4, 1), "reserved"),
+                        ((3, 5, 0.7, None, 0, 0), "kind")]:
+        req.prf = tno.tno_prf(*bad)
+        rc, msg = tno.tno_search_validate(req, out)
+        assert rc == tno.TNO_E_INVAL and needle in msg, msg
+    req.prf = tno.tno_prf(tno.TNO_PRF_TABLE, 5, 0.0, tab.ctypes.data_as(ctypes.c_void_p), 4, 0)
+    for v in (np.nan, np.inf, 300.0):
+        jit[2, 1] = v
+        rc, msg = tno.tno_search_validate(req, out)
+        assert rc == tno.TNO_E_INVAL and "jitter" in msg, msg
+    jit[2, 1] = 40.0       # a large but legal excursion widens the staged border
+    assert tno.tno_search_validate(req, out)[0] == tno.TNO_OK
+    assert tno.tno_search_footprint(req, out) > f_tab
