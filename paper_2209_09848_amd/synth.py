@@ -354,3 +354,114 @@ def make_ffi_like_torch(H: int, W: int, T: int, device, J_speeds: int = 10, J_di
                torch.from_numpy(x).to(device))
         R.index_put_(idx, torch.from_numpy(v.astype(np.float32)).to(device), accumulate=True)
     return R, sigma, times, t_ref, vel, src
+
+
+# ---------------------------------------------------------------- raw frames for the background re-fit
+
+def scattered_light_field(tt, y, x, H: int, W: int):
+    """A smooth scattered-light pattern (a few broad glows whose brightness
+    drifts over the sector), evaluated at times tt [T] (days from the first
+    frame) and pixel coordinates y [..], x [..] (broadcast).  Works on numpy
+    arrays or torch tensors."""
+    lib = np if isinstance(y, np.ndarray) else __import__("torch")
+    L = float(max(H, W))
+    out = 0.0
+    for (cy, cx, s, a, per) in ((-0.3, 0.2, 0.6, 40.0, 13.7), (1.1, 0.9, 0.5, 25.0, 9.3),
+                                (0.4, -0.4, 0.9, 15.0, 27.0)):
+        g = lib.exp(-((y - cy * H) ** 2 + (x - cx * W) ** 2) / (2.0 * (s * L) ** 2))
+        amp = a * (1.0 + 0.5 * lib.sin(2.0 * math.pi * tt / per))
+        out = out + amp * g
+    return out
+
+
+def make_refit_problem(H: int, W: int, T: int, device="cpu", n_sl: int = 64,
+                       n_stars: int | None = None, noise: float = 1.0,
+                       cosmic_frac: float = 2e-4, n_streaks: int = 4, config_id: int = 7,
+                       n_sources: int = 0, source_amp=(0.3, 1.0), J_speeds: int = 10,
+                       J_dirs: int = 10, chunk: int = 64):
+    """Raw TESS-like frames for the background re-fit (Sec. 3.1 eq. 1):
+    smooth scattered light, a static sky with stars that move with the
+    pointing jitter, Gaussian noise of standard deviation `noise`, cosmic-ray
+    hits and a few fast asteroid streaks (the unmodelled transients of Sec.
+    3.2), and optionally faint slow movers on bank trajectories.
+
+    Returns dict: D (torch float32 [T][H][W] on `device`), S (numpy float32
+    [T][n_sl][n_sl]: the scattered light sampled at the centres of an n_sl x
+    n_sl grid of cells), jitter [T][2], times, t_ref, vel, sources, noise."""
+    import torch
+    times = times_with_gap(T, T // 2)
+    t_ref = float(times[0])
+    tt = times - times[0]
+    jit = jitter_series(rng(config_id, 4), T, amp=0.15)
+    g = rng(config_id, 5)
+    if n_stars is None:
+        n_stars = max(1, int(H * W / 800))
+    sy = g.uniform(-3, H + 3, n_stars)
+    sx = g.uniform(-3, W + 3, n_stars)
+    sflux = noise * 10.0 ** g.uniform(1.0, 5.0, n_stars)
+    # low-resolution samples of the scattered light at grid-cell centres
+    gy = (np.arange(n_sl) + 0.5) * H / n_sl - 0.5
+    gx = (np.arange(n_sl) + 0.5) * W / n_sl - 0.5
+    S = scattered_light_field(tt[:, None, None], gy[None, :, None], gx[None, None, :], H, W)
+    S = np.asarray(S, np.float32)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(np.random.SeedSequence([2209, config_id, 6]).generate_state(1)[0]))
+    D = torch.empty((T, H, W), dtype=torch.float32, device=device)
+    yy = torch.arange(H, device=device, dtype=torch.float64)[:, None]
+    xx = torch.arange(W, device=device, dtype=torch.float64)[None, :]
+    sky = 100.0 + 0.002 * yy - 0.001 * xx
+    taps = torch.arange(-3, 4, device=device, dtype=torch.float64)
+    sy_t = torch.from_numpy(sy).to(device)
+    sx_t = torch.from_numpy(sx).to(device)
+    sf_t = torch.from_numpy(sflux).to(device)
+    r2 = 1.0 / math.sqrt(2.0)
+    for k0 in range(0, T, chunk):
+        k1 = min(T, k0 + chunk)
+        n = k1 - k0
+        tk = torch.from_numpy(tt[k0:k1]).to(device)[:, None, None]
+        frame = scattered_light_field(tk, yy[None], xx[None], H, W) + sky[None]
+        # stars at their jittered positions, Gaussian PSF (sigma 0.7) integrated over pixels
+        jx = torch.from_numpy(jit[k0:k1, 0]).to(device)[:, None]
+        jy = torch.from_numpy(jit[k0:k1, 1]).to(device)[:, None]
+        px = sx_t[None] + jx
+        py = sy_t[None] + jy
+        cx = torch.floor(px + 0.5)
+        cy = torch.floor(py + 0.5)
+        def share(c, p):
+            lo = (c[..., None] + taps - 0.5 - p[..., None]) / 0.7 * r2
+            hi = (c[..., None] + taps + 0.5 - p[..., None]) / 0.7 * r2
+            return 0.5 * (torch.erf(hi) - torch.erf(lo))
+        wy = share(cy, py)                      # [n][stars][7]
+        wx = share(cx, px)
+        val = (sf_t[None, :, None, None] * wy[..., :, None] * wx[..., None, :])
+        Y = (cy[..., None] + taps).long()[..., :, None].expand(val.shape)
+        X = (cx[..., None] + taps).long()[..., None, :].expand(val.shape)
+        K = torch.arange(n, device=device)[:, None, None, None].expand(val.shape)
+        ok = (Y >= 0) & (Y < H) & (X >= 0) & (X < W)
+        frame.index_put_((K[ok], Y[ok], X[ok]), val[ok], accumulate=True)
+        frame += noise * torch.randn((n, H, W), generator=gen, device=device, dtype=torch.float64)
+        hits = torch.rand((n, H, W), generator=gen, device=device) < cosmic_frac
+        frame += hits * noise * (20.0 + 480.0 * torch.rand((n, H, W), generator=gen, device=device,
+                                                            dtype=torch.float64))
+        D[k0:k1] = frame.to(torch.float32)
+    # fast asteroid streaks: bright, a few px per frame, over a stretch of frames
+    for _ in range(n_streaks):
+        k0 = int(g.integers(0, max(1, T - 40)))
+        k1 = min(T, k0 + int(g.integers(10, 40)))
+        y0, x0 = g.uniform(0, H), g.uniform(0, W)
+        vy, vx = g.uniform(-6, 6), g.uniform(-6, 6)
+        for k in range(k0, k1):
+            yk, xk = int(round(y0 + vy * (k - k0))), int(round(x0 + vx * (k - k0)))
+            if 0 <= yk < H and 0 <= xk < W:
+                D[k, yk, xk] += float(noise * 300.0)
+    vel = grid_speeds_directions(J_speeds, J_dirs)
+    src = []
+    if n_sources:
+        src = draw_sources(rng(config_id, 2), n_sources, vel, H, W, times, t_ref,
+                           source_amp[0], source_amp[1], min_sep=min(64.0, 0.25 * min(H, W)))
+        k, y, x, v = render_sources((T, H, W), times, t_ref, src, jitter=jit)
+        D.index_put_((torch.from_numpy(k).to(device), torch.from_numpy(y).to(device),
+                      torch.from_numpy(x).to(device)),
+                     torch.from_numpy((v * noise).astype(np.float32)).to(device), accumulate=True)
+    return {"D": D, "S": S, "jitter": jit, "times": times, "t_ref": t_ref, "vel": vel,
+            "sources": src, "noise": noise}
