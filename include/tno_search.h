@@ -243,6 +243,58 @@ void tno_search_destroy(tno_search *h);
 int tno_quantize(int32_t n_frames, int32_t height, int32_t width, int32_t dtype,
                  const float *residuals, void *codes, float *tile_scales, void *stream);
 
+/* ---------------------------------------------------------------- background re-fit */
+
+/* The per-pixel re-fit that turns raw frames into the residual stack and
+ * noise map the search reads (Sec. 3.1 eq. 1-3, Sec. 3.2 noise model).
+ *
+ * Per pixel, y_t = D_t - U(S_t): the raw frame minus the fixed low-resolution
+ * scattered light upsampled bilinearly (grid point (a, b) at pixel
+ * ((a + 1/2) H/sl_height - 1/2, (b + 1/2) W/sl_width - 1/2), edge values
+ * beyond the outermost points).  y is regressed on the basis
+ * x_t = (1, tx, ty, tx^2, ty^2, tx ty) of the frame's jitter (tx, ty); the one
+ * Gram matrix inverse serves every pixel.  The Huber loss of eq. 3 is
+ * minimised by a least-squares start and `iterations` rounds of least squares
+ * on pseudo-data X beta + clip(y - X beta, -delta, delta).  beta = (B, B_x,
+ * B_y, B_xx, B_yy, B_xy).  Noise model: pixels with B > bright_threshold are
+ * masked (residuals 0, sigma 0); sigma0 is the rms of the other pixels'
+ * residuals, then `sigma_rounds` times the rms of those within clip_sigma *
+ * sigma0; residual samples beyond clip_sigma * sigma0 are set to 0.
+ * Arithmetic is FP64; residuals are stored as FP32. */
+typedef struct {
+    int32_t height, width;       /* H, W > 0 */
+    int32_t n_frames;            /* T >= 6 */
+    int32_t sl_height, sl_width; /* scattered-light grid, >= 1 with `scattered`; else ignored */
+    const float *data;           /* [T][H][W] raw frames D_t */
+    const float *scattered;      /* [T][sl_height][sl_width] fixed scattered light, or NULL */
+    const double *jitter;        /* [T][2] = (tx, ty) pixels, finite, not degenerate (the
+                                    basis must have full rank: TNO_E_INVAL otherwise) */
+    double delta;                /* Huber threshold delta_0 in data units, > 0 (inf: least squares) */
+    double bright_threshold;     /* mask pixels whose B exceeds this (inf: none; not NaN) */
+    double clip_sigma;           /* kappa > 0 of the sigma rounds and the transient clip (inf: none) */
+    int32_t iterations;          /* clip-and-solve rounds after the least-squares start, 0..1000 */
+    int32_t sigma_rounds;        /* clipped re-estimates of sigma0, 0..100 */
+    uint32_t flags;              /* must be 0: every pointer is device memory */
+    uint32_t reserved;           /* must be 0 */
+} tno_refit_request;
+
+typedef struct {
+    float *residuals;            /* [T][H][W] residual stack for the search (device) */
+    float *sigma;                /* [H][W] sigma0, 0 at masked pixels (device) */
+    double *coeffs;              /* [6][H][W] beta (device), or NULL */
+    double sigma0;               /* written: the common noise sigma */
+    int64_t n_clipped;           /* written: residual samples set to 0 by the clip */
+    int64_t n_masked;            /* written: bright pixels */
+    double device_ms;            /* written: device time of the re-fit (HIP events) */
+} tno_refit_outputs;
+
+/* Run the re-fit on `stream` (hipStream_t, NULL: the default stream) and wait
+ * for it.  Allocates and frees its own scratch (the per-pixel coefficients
+ * when coeffs is NULL, and a few KB of partial sums).  Returns TNO_OK,
+ * TNO_E_INVAL (bad arguments, non-finite jitter, singular basis), TNO_E_NOMEM
+ * or TNO_E_DEVICE; tno_search_last_error() holds the message of a refusal. */
+int tno_refit(const tno_refit_request *req, tno_refit_outputs *out, void *stream);
+
 /* ---------------------------------------------------------------- host-only helpers */
 
 /* Check a request and outputs without touching a GPU (the same checks submit

@@ -69,6 +69,17 @@ def upsample(S, H: int, W: int) -> np.ndarray:
     return top * wy0[None, :, None] + bot * wy1[None, :, None]
 
 
+def upsample_at(S, H: int, W: int, ys, xs) -> np.ndarray:
+    """U(S) of an H x W image at the listed pixels only: [T][len(ys)]."""
+    S = np.asarray(S, np.float64)
+    T, ny, nx = S.shape
+    y0, y1, wy0, wy1 = (v[np.asarray(ys)] for v in upsample_axis(ny, H))
+    x0, x1, wx0, wx1 = (v[np.asarray(xs)] for v in upsample_axis(nx, W))
+    top = S[:, y0, x0] * wx0 + S[:, y0, x1] * wx1
+    bot = S[:, y1, x0] * wx0 + S[:, y1, x1] * wx1
+    return top * wy0 + bot * wy1
+
+
 def basis(jitter) -> np.ndarray:
     """X [T][6]: (1, x, y, x^2, y^2, x y) of each frame's jitter (x, y)."""
     j = np.asarray(jitter, np.float64)

@@ -129,4 +129,7 @@ hipError_t launch_quantize(hipStream_t st, int dtype, const float *R, int T, int
 
 constexpr int TOPK_CHUNK = 8192;
 
+// Set the thread's last-error message (read by tno_search_last_error).
+void record_error(const char *fmt, ...);
+
 }  // namespace tno

@@ -884,6 +884,19 @@ uint64_t tno_search_footprint(const tno_request *req, const tno_outputs *out)
 
 const char *tno_search_last_error(void) { return g_last_error; }
 
+}  // extern "C"
+
+// The message of a refusal by another part of the library (same thread-local slot).
+void tno::record_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+}
+
+extern "C" {
+
 int tno_search_create(const tno_config *cfg, tno_search **out_handle)
 {
     if (!cfg || !out_handle) {

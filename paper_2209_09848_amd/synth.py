@@ -378,12 +378,13 @@ def make_refit_problem(H: int, W: int, T: int, device="cpu", n_sl: int = 64,
                        n_stars: int | None = None, noise: float = 1.0,
                        cosmic_frac: float = 2e-4, n_streaks: int = 4, config_id: int = 7,
                        n_sources: int = 0, source_amp=(0.3, 1.0), J_speeds: int = 10,
-                       J_dirs: int = 10, chunk: int = 64):
+                       J_dirs: int = 10, chunk: int = 64, source_min_speed: int = 0):
     """Raw TESS-like frames for the background re-fit (Sec. 3.1 eq. 1):
     smooth scattered light, a static sky with stars that move with the
     pointing jitter, Gaussian noise of standard deviation `noise`, cosmic-ray
     hits and a few fast asteroid streaks (the unmodelled transients of Sec.
-    3.2), and optionally faint slow movers on bank trajectories.
+    3.2), and optionally faint slow movers on bank trajectories (those of
+    speed index >= source_min_speed).
 
     Returns dict: D (torch float32 [T][H][W] on `device`), S (numpy float32
     [T][n_sl][n_sl]: the scattered light sampled at the centres of an n_sl x
@@ -457,8 +458,11 @@ def make_refit_problem(H: int, W: int, T: int, device="cpu", n_sl: int = 64,
     vel = grid_speeds_directions(J_speeds, J_dirs)
     src = []
     if n_sources:
-        src = draw_sources(rng(config_id, 2), n_sources, vel, H, W, times, t_ref,
+        j0 = source_min_speed * J_dirs
+        src = draw_sources(rng(config_id, 2), n_sources, vel[j0:], H, W, times, t_ref,
                            source_amp[0], source_amp[1], min_sep=min(64.0, 0.25 * min(H, W)))
+        for s_ in src:
+            s_.traj += j0
         k, y, x, v = render_sources((T, H, W), times, t_ref, src, jitter=jit)
         D.index_put_((torch.from_numpy(k).to(device), torch.from_numpy(y).to(device),
                       torch.from_numpy(x).to(device)),

@@ -97,8 +97,24 @@ class tno_result(ctypes.Structure):
                 ("reduce_ms", ctypes.c_double), ("message", ctypes.c_char * 160)]
 
 
+class tno_refit_request(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32), ("n_frames", ctypes.c_int32),
+                ("sl_height", ctypes.c_int32), ("sl_width", ctypes.c_int32), ("data", _vp),
+                ("scattered", _vp), ("jitter", _vp), ("delta", ctypes.c_double),
+                ("bright_threshold", ctypes.c_double), ("clip_sigma", ctypes.c_double),
+                ("iterations", ctypes.c_int32), ("sigma_rounds", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class tno_refit_outputs(ctypes.Structure):
+    _fields_ = [("residuals", _vp), ("sigma", _vp), ("coeffs", _vp), ("sigma0", ctypes.c_double),
+                ("n_clipped", ctypes.c_int64), ("n_masked", ctypes.c_int64),
+                ("device_ms", ctypes.c_double)]
+
+
 EXPORTS = ("tno_search_create", "tno_search_submit", "tno_search_poll", "tno_search_destroy",
-           "tno_search_validate", "tno_search_footprint", "tno_search_last_error", "tno_quantize")
+           "tno_search_validate", "tno_search_footprint", "tno_search_last_error", "tno_quantize",
+           "tno_refit")
 
 
 class TnoError(RuntimeError):
@@ -136,6 +152,8 @@ def load(path: str = LIB_PATH):
     lib.tno_search_last_error.restype = ctypes.c_char_p
     lib.tno_quantize.argtypes = [ctypes.c_int32] * 4 + [_vp, _vp, _vp, _vp]
     lib.tno_quantize.restype = ctypes.c_int
+    lib.tno_refit.argtypes = [P(tno_refit_request), P(tno_refit_outputs), _vp]
+    lib.tno_refit.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -359,3 +377,46 @@ def search_tensors(R, sigma, times, vel, *, top_k=10, maps=True, handle: Search 
         if own:
             h.close()
     return o, res
+
+
+# ------------------------------------------------------------------ background re-fit
+
+def tno_refit(req: tno_refit_request, out: tno_refit_outputs, stream=None) -> int:
+    return int(load().tno_refit(ctypes.byref(req), ctypes.byref(out),
+                                ctypes.c_void_p(stream) if stream else None))
+
+
+def refit_tensors(D, jitter, *, scattered=None, delta=1.345, iterations=5, bright_threshold=math.inf,
+                  clip_sigma=5.0, sigma_rounds=3, coeffs=True, stream=None):
+    """Per-pixel background re-fit of raw frames D (float32 [T][H][W] on the
+    GPU) with jitter (float64 [T][2]) and optional low-resolution scattered
+    light (float32 [T][ny][nx]), all device tensors.  Returns (dict with
+    residuals, sigma, coeffs tensors, tno_refit_outputs)."""
+    import torch
+    T, H, W = (int(v) for v in D.shape)
+    req = tno_refit_request()
+    req.height, req.width, req.n_frames = H, W, T
+    if scattered is not None:
+        req.sl_height, req.sl_width = int(scattered.shape[1]), int(scattered.shape[2])
+    req.data = _ptr(D)
+    req.scattered = _ptr(scattered)
+    req.jitter = _ptr(jitter)
+    req.delta = float(delta)
+    req.bright_threshold = float(bright_threshold)
+    req.clip_sigma = float(clip_sigma)
+    req.iterations = int(iterations)
+    req.sigma_rounds = int(sigma_rounds)
+    o = {"residuals": torch.empty((T, H, W), dtype=torch.float32, device=D.device),
+         "sigma": torch.empty((H, W), dtype=torch.float32, device=D.device)}
+    if coeffs:
+        o["coeffs"] = torch.empty((6, H, W), dtype=torch.float64, device=D.device)
+    out = tno_refit_outputs()
+    out.residuals = _ptr(o["residuals"])
+    out.sigma = _ptr(o["sigma"])
+    out.coeffs = _ptr(o.get("coeffs"))
+    if stream is None:
+        stream = torch.cuda.current_stream(D.device).cuda_stream
+    rc = tno_refit(req, out, stream)
+    if rc != TNO_OK:
+        raise TnoError(rc, tno_search_last_error())
+    return o, out

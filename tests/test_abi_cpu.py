@@ -154,3 +154,32 @@ def test_validate_tabulated_prf_and_jitter():
     jit[2, 1] = 40.0       # a large but legal excursion widens the staged border
     assert tno.tno_search_validate(req, out)[0] == tno.TNO_OK
     assert tno.tno_search_footprint(req, out) > f_tab
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """gcc compiles the header and prints every field offset and struct size;
+    the ctypes mirrors must agree byte for byte."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = [tno.tno_config, tno.tno_prf, tno.tno_request, tno.tno_peak, tno.tno_candidate,
+               tno.tno_detection, tno.tno_outputs, tno.tno_result, tno.tno_refit_request,
+               tno.tno_refit_outputs]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tno_search.h"', 'int main(void) {']
+    for st in structs:
+        n = st.__name__
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (n, n))
+        for f, _ in st._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (n, f, n, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.rsplit(" ", 1) for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for st in structs:
+        n = st.__name__
+        assert int(got["%s size" % n]) == ctypes.sizeof(st), n
+        for f, _ in st._fields_:
+            assert int(got["%s.%s" % (n, f)]) == getattr(st, f).offset, (n, f)

@@ -1,0 +1,203 @@
+"""GPU parity of the per-pixel background re-fit (Sec. 3.1 eq. 1-3, Sec. 3.2
+noise model) through the C ABI against the FP64 oracle: full maps on small
+raw stacks with scattered light, jittered stars, cosmic rays and streaks;
+edge cases; sampled pixels at the full FFI size; and the re-fit feeding the
+search end to end."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle, refit
+from paper_2209_09848_amd import synth, tno
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _to(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _gpu(D, S, jit, **kw):
+    o, out = tno.refit_tensors(D if isinstance(D, torch.Tensor) else _to(np.asarray(D, np.float32)),
+                               _to(jit), scattered=None if S is None else _to(S), **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in o.items()}, out
+
+
+def _compare(g, out, o, kappa):
+    beta_o = o["beta"]
+    err_b = np.abs(g["coeffs"] - beta_o) / (1.0 + np.abs(beta_o))
+    assert err_b.max() <= 1e-9, err_b.max()
+    assert out.n_masked == o["n_masked"]
+    assert abs(out.sigma0 - o["sigma0"]) <= 1e-10 * max(1.0, o["sigma0"])
+    np.testing.assert_array_equal(g["sigma"] == 0, o["sigma"] == 0)
+    # (sigma0 itself is compared to 1e-10 absolute: with no degrees of freedom
+    # left, T = 6, it is rounding noise on both sides)
+    assert np.all(np.abs(g["sigma"] - o["sigma"]) <= 1e-7 * o["sigma"] + 1e-10 * max(1.0, o["sigma0"]))
+    # clip decisions agree except where |r| sits on kappa * sigma0 to rounding
+    lim = kappa * o["sigma0"]
+    border = np.abs(np.abs(o["resid"]) - lim) <= 1e-9 * max(lim, 1.0)
+    gz = (g["residuals"] == 0) & (o["R"] != 0)
+    oz = (o["R"] == 0) & (g["residuals"] != 0)
+    assert not np.any((gz | oz) & ~border)
+    assert abs(out.n_clipped - o["n_clipped"]) <= int(border.sum())
+    both = ~(gz | oz)
+    tol = 2e-7 * np.abs(o["R"]) + 1e-9 * (1.0 + o["sigma0"])
+    assert np.all(np.abs(g["residuals"] - o["R"])[both] <= tol[both])
+
+
+@pytest.mark.parametrize("H,W,T,n_sl,iters", [(40, 70, 90, 5, 6), (33, 130, 64, 8, 3),
+                                              (17, 19, 200, 3, 10)])
+def test_refit_parity(H, W, T, n_sl, iters):
+    print("refit case", H, W, T, n_sl, iters, flush=True)
+    p = synth.make_refit_problem(H, W, T, device=DEV, n_sl=n_sl, cosmic_frac=1e-3, n_streaks=2,
+                                 config_id=40 + T)
+    D = p["D"]
+    kw = dict(delta=1.345, iterations=iters, bright_threshold=300.0, clip_sigma=5.0, sigma_rounds=3)
+    g, out = _gpu(D, p["S"], p["jitter"], **kw)
+    o = refit.pipeline(D.cpu().numpy(), p["S"], p["jitter"], 1.345, iters, 300.0, 5.0, 3)
+    print("sigma0 %.6f clipped %d masked %d" % (out.sigma0, out.n_clipped, out.n_masked), flush=True)
+    assert out.n_clipped > 0 and out.n_masked > 0
+    _compare(g, out, o, 5.0)
+
+
+@pytest.mark.parametrize("case", ["no_scattered_light", "least_squares", "all_masked", "minimal_T",
+                                  "one_pixel", "thin_strip", "no_clip"])
+def test_refit_edge_cases(case):
+    H, W, T = 24, 40, 50
+    kw = dict(delta=1.345, iterations=4, bright_threshold=2000.0, clip_sigma=5.0, sigma_rounds=2)
+    S_on = True
+    if case == "minimal_T":
+        T = 6
+    if case == "one_pixel":
+        H = W = 1
+        S_on = False
+    if case == "thin_strip":
+        H, W = 3, 301
+    p = synth.make_refit_problem(max(H, 2), max(W, 2), T, device=DEV, n_sl=2, config_id=77)
+    D = p["D"][:, :H, :W].contiguous()
+    S = p["S"] if S_on and case != "no_scattered_light" else None
+    if case == "least_squares":
+        kw.update(delta=math.inf, iterations=0)
+    if case == "all_masked":
+        kw.update(bright_threshold=-math.inf)
+    if case == "no_clip":
+        kw.update(clip_sigma=math.inf)
+    print("refit edge", case, flush=True)
+    g, out = _gpu(D, S, p["jitter"], **kw)
+    o = refit.pipeline(D.cpu().numpy(), S, p["jitter"], kw["delta"], kw["iterations"],
+                       kw["bright_threshold"], kw["clip_sigma"], kw["sigma_rounds"])
+    if case == "all_masked":
+        assert out.n_masked == H * W and out.sigma0 == 0.0 and np.all(g["residuals"] == 0)
+    if case == "no_clip":
+        assert out.n_clipped == 0
+    _compare(g, out, o, kw["clip_sigma"])
+
+
+def test_refit_rejects_degenerate_and_nonfinite_jitter():
+    T, H, W = 20, 8, 8
+    D = torch.zeros((T, H, W), dtype=torch.float32, device=DEV)
+    for jit, needle in [(np.zeros((T, 2)), "singular"), (np.full((T, 2), 0.1), "singular")]:
+        with pytest.raises(tno.TnoError) as e:
+            tno.refit_tensors(D, _to(jit))
+        assert e.value.code == tno.TNO_E_INVAL and needle in str(e.value)
+    jit = synth.jitter_series(np.random.default_rng(1), T)
+    jit[5, 1] = np.nan
+    with pytest.raises(tno.TnoError) as e:
+        tno.refit_tensors(D, _to(jit))
+    assert "non-finite" in str(e.value)
+    with pytest.raises(tno.TnoError):
+        tno.refit_tensors(D[:5].contiguous(), _to(jit[:5]))        # fewer frames than basis terms
+
+
+@pytest.mark.slow
+def test_refit_full_ffi_size_sampled_parity():
+    """2048 x 2048 px x 1000 frames: the re-fit's time, beta and residuals at
+    sampled pixels against the oracle, and sigma0 and the clip count against
+    an independent torch recomputation from the GPU's coefficients."""
+    H = W = 2048
+    T = 1000
+    print("generating raw FFI-size frames", flush=True)
+    p = synth.make_refit_problem(H, W, T, device=DEV, n_sl=64, config_id=90)
+    D, S, jit = p["D"], p["S"], p["jitter"]
+    kw = dict(delta=1.345, iterations=5, bright_threshold=5000.0, clip_sigma=5.0, sigma_rounds=3)
+    o, out = tno.refit_tensors(D, _to(jit), scattered=_to(S), **kw)
+    torch.cuda.synchronize()
+    print("refit %.1f ms sigma0 %.5f clipped %d masked %d" % (out.device_ms, out.sigma0,
+                                                             out.n_clipped, out.n_masked), flush=True)
+    g = np.random.default_rng(5)
+    ys = np.concatenate([[0, 0, H - 1, H - 1, 1024], g.integers(0, H, 59)])
+    xs = np.concatenate([[0, W - 1, 0, W - 1, 1024], g.integers(0, W, 59)])
+    yv = D[:, torch.from_numpy(ys).to(DEV), torch.from_numpy(xs).to(DEV)].cpu().numpy().astype(np.float64)
+    y = yv - refit.upsample_at(S, H, W, ys, xs)
+    beta_o, resid_o = refit.refit(y[:, None, :], None, jit, 1.345, 5)
+    cb = o["coeffs"][:, ys, xs].cpu().numpy()
+    assert (np.abs(cb - beta_o[:, 0, :]) / (1.0 + np.abs(beta_o[:, 0, :]))).max() <= 1e-9
+    Rg = o["residuals"][:, ys, xs].cpu().numpy()
+    masked = beta_o[0, 0, :] > 5000.0
+    lim = 5.0 * out.sigma0
+    ro = resid_o[:, 0, :]
+    expect = np.where(masked[None] | (np.abs(ro) > lim), 0.0, ro)
+    border = np.abs(np.abs(ro) - lim) <= 1e-9 * lim
+    ok = (np.abs(Rg - expect) <= 2e-7 * np.abs(expect) + 1e-9 * (1 + out.sigma0)) | border
+    assert ok.all()
+    # sigma0 and the clip count from the GPU's coefficients, recomputed in torch
+    X = torch.from_numpy(refit.basis(jit)).to(DEV)
+    beta = o["coeffs"].reshape(6, -1)
+    keep = beta[0] <= 5000.0
+    Sd = torch.from_numpy(S.astype(np.float64)).to(DEV)
+    def sums(limit):
+        s = torch.zeros((), dtype=torch.float64, device=DEV)
+        c = torch.zeros((), dtype=torch.float64, device=DEV)
+        for k0 in range(0, T, 50):
+            k1 = min(T, k0 + 50)
+            U = torch.nn.functional.interpolate(Sd[k0:k1][None], size=(H, W), mode="bilinear",
+                                                align_corners=False)[0]
+            r = (D[k0:k1].double() - U).reshape(k1 - k0, -1) - X[k0:k1] @ beta
+            r = r[:, keep]
+            inside = r.abs() <= limit
+            s += (r * r * inside).sum()
+            c += inside.sum()
+        return s, c
+    s, c = sums(math.inf)
+    sig = math.sqrt(float(s / c))
+    for _ in range(3):
+        s, c = sums(5.0 * sig)
+        sig = math.sqrt(float(s / c))
+    assert abs(sig - out.sigma0) <= 1e-9 * sig
+    assert int(keep.numel() - keep.sum()) == out.n_masked
+
+
+def test_refit_then_search_finds_the_injected_movers():
+    """Raw frames with faint slow movers: the re-fit's residual stack and noise
+    map go straight into the search; the injected sources are the top
+    candidates, and the search's SNR there matches the oracle's search on the
+    oracle's re-fit."""
+    H, W, T = 192, 256, 240
+    # movers of at least 0.07 px/frame: a slower one would sit on one pixel for
+    # much of the 5-day stack and the per-pixel background would absorb it
+    p = synth.make_refit_problem(H, W, T, device=DEV, n_sl=6, n_sources=2, source_amp=(2.0, 2.5),
+                                 config_id=11, n_streaks=1, source_min_speed=6)
+    kw = dict(delta=1.345, iterations=5, bright_threshold=150.0, clip_sigma=5.0, sigma_rounds=3)
+    o, out = tno.refit_tensors(p["D"], _to(p["jitter"]), scattered=_to(p["S"]), **kw)
+    vel = p["vel"]
+    res_o, res = tno.search_tensors(o["residuals"], o["sigma"], _to(p["times"]), _to(vel),
+                                    t_ref=p["t_ref"], top_k=20, jitter=_to(p["jitter"]))
+    torch.cuda.synchronize()
+    cands = tno.decode_candidates(res_o["topk"], res.n_topk)
+    top = {(c[2], c[3], c[4]) for c in cands[:6]}
+    orf = refit.pipeline(p["D"].cpu().numpy(), p["S"], p["jitter"], 1.345, 5, 150.0, 5.0, 3)
+    for s in p["sources"]:
+        yr, xr = int(math.floor(s.y + 0.5)), int(math.floor(s.x + 0.5))
+        near = [c for c in top if c[0] == s.traj and abs(c[1] - yr) <= 1 and abs(c[2] - xr) <= 1]
+        assert near, (s, cands[:6])
+        j, y, x = near[0]
+        ora = oracle.hypotheses(orf["R"].astype(np.float32), orf["sigma"].astype(np.float32),
+                                p["times"], p["t_ref"], vel, [j], [y], [x], jitter=p["jitter"])
+        g = res_o["snr"][j, y, x].item()
+        assert abs(g - ora["snr"][0]) <= 2e-5 * max(1.0, abs(ora["snr"][0]))
+        print("source traj %d at (%d, %d): SNR %.2f" % (j, y, x, g), flush=True)

@@ -39,6 +39,14 @@ def test_upsample_reproduces_constants_and_interior_planes():
     np.testing.assert_allclose(U[np.ix_(inner, innerx)], plane[np.ix_(inner, innerx)], atol=1e-12)
 
 
+def test_upsample_at_selected_pixels_matches_the_full_map():
+    g = np.random.default_rng(3)
+    S = g.standard_normal((4, 6, 9))
+    full = refit.upsample(S, 41, 77)
+    ys, xs = g.integers(0, 41, 30), g.integers(0, 77, 30)
+    np.testing.assert_array_equal(refit.upsample_at(S, 41, 77, ys, xs), full[:, ys, xs])
+
+
 def _problem(seed, T=60, H=5, W=7, outliers=0.0, noise=0.3):
     g = np.random.default_rng(seed)
     jit = np.column_stack([0.15 * np.sin(np.arange(T) / 7.0) + 0.05 * g.standard_normal(T),
