@@ -29,6 +29,8 @@ namespace tno {
 // ------------------------------------------------------------------ helpers
 
 typedef __attribute__((address_space(4))) int32_t cint32_t;   // constant address space
+// Word 3 of a raw (unformatted, stride 0) buffer resource on gfx9-family GPUs.
+constexpr int BUF_DWORD3 = 0x00020000;
 
 __device__ __forceinline__ uint32_t ordered_key(float f)
 {
@@ -550,15 +552,19 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
 
     // This thread's staging slots: window group idx = tid + NT*it at (row r,
     // group g), global offset r * Wp4 + g from the window origin.
-    int soff[NLD];
+    // (as byte offsets: below 2^32 since WY * Wp4 * 16 is)
+    uint32_t soff[NLD];
 #pragma unroll
     for (int it = 0; it < NLD; ++it) {
         const int idx = tid + NT * it;
         const int r = idx / NG;
-        soff[it] = r * a.Wp4 + (idx - r * NG);
+        soff[it] = (uint32_t)(r * a.Wp4 + (idx - r * NG)) * 16u;
     }
-    // only the last slot can fall past the window
+    // only the last slot can fall past the window; such a lane's buffer
+    // offset is set past every resource, so it reads 0 and touches no memory
     const bool last_ok = tid + NT * (NLD - 1) < NWIN;
+    if (!last_ok)
+        soff[NLD - 1] = 0x80000000u;
 
     // the table is read-only for the whole launch: read it through the
     // constant address space so its wave-uniform entries stay scalar loads
@@ -573,11 +579,19 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
         const int ag = ox >> 2;      // floor division (arithmetic shift)
         const float4 *Zk = a.Z4 + (size_t)k * frame4;
         if (oy >= 0 && oy + WY <= a.Hp && ag >= 0 && ag + NG <= a.Wp4) {
-            const float4 *b = Zk + (size_t)oy * a.Wp4 + ag;
+            // buffer loads from a resource at the window origin (scalar
+            // registers) plus 32-bit lane offsets; the resource ends with the
+            // frame (at most 2^31 - 1 bytes on), so no load reaches past it
+            const size_t o0 = (size_t)oy * a.Wp4 + ag;
+            const size_t rem = (frame4 - o0) * 16;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(Zk + o0), (short)0, (int)(rem < 0x7FFFFFFFu ? rem : 0x7FFFFFFFu), BUF_DWORD3);
 #pragma unroll
-            for (int it = 0; it < NLD; ++it)
-                if (it < NLD - 1 || last_ok)
-                    pre[it] = b[soff[it]];
+            for (int it = 0; it < NLD; ++it) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)soff[it], 0, 0);
+                pre[it] = make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]),
+                                      __uint_as_float(v[2]), __uint_as_float(v[3]));
+            }
         } else {
 #pragma unroll
             for (int it = 0; it < NLD; ++it) {
@@ -656,9 +670,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
                 for (int t = 0; t < NV; ++t)
                     pt[t] = wrow + ((s0 + t) & 1) * HALF + ((s0 + t) >> 1);
             }
-#pragma unroll
-            for (int rr = 0; rr < RPL + S - 1; ++rr) {
-                float v[NV];
+            auto row = [&](int rr, float (&v)[NV]) {
 #pragma unroll
                 for (int t = 0; t < NV; ++t) {
                     if constexpr (SPLIT)
@@ -666,6 +678,16 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
                     else
                         v[t] = pt[t][rr * LH];
                 }
+            };
+            // window rows are read one row ahead of their use (the loop is
+            // unrolled, so the two buffers are register renames)
+            float vbuf[2][NV];
+            row(0, vbuf[0]);
+#pragma unroll
+            for (int rr = 0; rr < RPL + S - 1; ++rr) {
+                if (rr + 1 < RPL + S - 1)
+                    row(rr + 1, vbuf[(rr + 1) & 1]);
+                const float (&v)[NV] = vbuf[rr & 1];
                 if constexpr (SEP) {
                     // horizontal pass of the row, streamed into the vertical pass
                     float hs[CPL];
