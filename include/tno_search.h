@@ -266,7 +266,7 @@ typedef struct {
     int32_t n_frames;            /* T >= 6 */
     int32_t sl_height, sl_width; /* scattered-light grid, >= 1 with `scattered`; else ignored */
     const float *data;           /* [T][H][W] raw frames D_t */
-    const float *scattered;      /* [T][sl_height][sl_width] fixed scattered light, or NULL */
+    const float *scattered;      /* [T][sl_height][sl_width] fixed scattered light (finite), or NULL */
     const double *jitter;        /* [T][2] = (tx, ty) pixels, finite, not degenerate (the
                                     basis must have full rank: TNO_E_INVAL otherwise) */
     double delta;                /* Huber threshold delta_0 in data units, > 0 (inf: least squares) */

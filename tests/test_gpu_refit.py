@@ -66,7 +66,8 @@ def test_refit_parity(H, W, T, n_sl, iters):
 
 
 @pytest.mark.parametrize("case", ["no_scattered_light", "least_squares", "all_masked", "minimal_T",
-                                  "one_pixel", "thin_strip", "no_clip"])
+                                  "one_pixel", "thin_strip", "no_clip", "one_column_grid",
+                                  "one_row_grid"])
 def test_refit_edge_cases(case):
     H, W, T = 24, 40, 50
     kw = dict(delta=1.345, iterations=4, bright_threshold=2000.0, clip_sigma=5.0, sigma_rounds=2)
@@ -81,6 +82,10 @@ def test_refit_edge_cases(case):
     p = synth.make_refit_problem(max(H, 2), max(W, 2), T, device=DEV, n_sl=2, config_id=77)
     D = p["D"][:, :H, :W].contiguous()
     S = p["S"] if S_on and case != "no_scattered_light" else None
+    if case == "one_column_grid":
+        S = np.ascontiguousarray(p["S"][:, :, :1])
+    if case == "one_row_grid":
+        S = np.ascontiguousarray(p["S"][:, :1, :])
     if case == "least_squares":
         kw.update(delta=math.inf, iterations=0)
     if case == "all_masked":
