@@ -329,10 +329,11 @@ def make_ffi_like(H: int, W: int, T: int, J_speeds: int = 10, J_dirs: int = 10,
 def make_ffi_like_torch(H: int, W: int, T: int, device, J_speeds: int = 10, J_dirs: int = 10,
                         n_sources: int = 30, amp=(0.05, 0.5), config_id: int = 2,
                         dex: float = 0.3, vmin: float = 0.01, vmax: float = 0.2,
-                        seed: int = 0):
+                        seed: int = 0, bank=None):
     """FFI-shaped problem drawn on `device` with torch's seeded generator
-    (for stacks too large to draw on the host quickly).  Returns
-    (R tensor [T][H][W] float32 on device, sigma numpy, times, t_ref, vel, sources)."""
+    (for stacks too large to draw on the host quickly); `bank` replaces the
+    speeds x directions grid.  Returns (R tensor [T][H][W] float32 on
+    device, sigma numpy, times, t_ref, vel, sources)."""
     import torch
     times = times_with_gap(T, T // 2)
     t_ref = float(times[0])
@@ -345,7 +346,7 @@ def make_ffi_like_torch(H: int, W: int, T: int, device, J_speeds: int = 10, J_di
         k1 = min(T, k0 + 64)
         R[k0:k1] = torch.randn((k1 - k0, H, W), generator=gen, device=device,
                                dtype=torch.float32) * sig_t
-    vel = grid_speeds_directions(J_speeds, J_dirs, vmin, vmax)
+    vel = grid_speeds_directions(J_speeds, J_dirs, vmin, vmax) if bank is None else np.asarray(bank)
     src = draw_sources(rng(config_id, 2, seed), n_sources, vel, H, W, times, t_ref,
                        amp[0], amp[1], min_sep=min(64.0, 0.25 * min(H, W)))
     if src:
