@@ -42,8 +42,14 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """SHA-256 (first 16 hex digits) of the kernel source with its // comments
+    and all whitespace removed: comment edits keep the counters valid, any
+    code change voids them."""
+    import re
+    with open(KERNEL_SOURCE) as f:
+        src = f.read()
+    code = re.sub(r"\s+", "", re.sub(r"//[^\n]*", "", src))
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def measured_traffic(updates_per_launch):

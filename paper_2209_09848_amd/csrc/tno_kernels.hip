@@ -506,17 +506,19 @@ hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a)
 
 // ------------------------------------------------------------------ k_search
 
-// One block = one (tile of 128 x SEARCH_TY start pixels, trajectory).  Per
-// frame k the block needs the window of Z its stamps cover at the frame's
-// integer shift: (TY+S-1) rows x (128+S-1) columns, staged as aligned float4
-// groups (the sub-float4 offset d is applied when reading).  The window of
-// frame k+1 is fetched into registers before frame k is computed and stored
-// into the other half of a double-buffered LDS window afterwards, so global
-// latency overlaps the arithmetic and one barrier per frame suffices.  Every
-// lane evaluates the separable stamp for its 2 columns x 8 rows: a horizontal
-// pass of S taps per window row streamed into a vertical pass of S taps.  The
-// table entry (shift, PRF taps) is wave-uniform (scalar loads).  Frame
-// partials accumulate in FP32 over FRAME_CHUNK frames, then into FP64.
+// One block = one (tile of (64 CPL) x (RPL NWAVE) start pixels, trajectory);
+// a lane owns CPL columns x RPL rows.  Per frame k the block needs the window
+// of Z its stamps cover at the frame's integer shift: (TY+S-1) rows x
+// (TX+S-1) columns, fetched as aligned float4 groups (buffer loads, the
+// sub-float4 offset d applied when reading) and staged de-interleaved into
+// LDS.  The window of frame k+1 is fetched into registers before frame k is
+// computed and stored into the other half of a double-buffered LDS window
+// afterwards, so global latency overlaps the arithmetic and one barrier per
+// frame suffices.  SEP: the separable stamp, a horizontal pass of S taps per
+// window row streamed into a vertical pass of S taps; otherwise the general
+// S x S stamp.  The table entry (shift, weights) is wave-uniform (scalar
+// loads).  Frame partials accumulate in FP32 over FRAME_CHUNK frames, then
+// into FP64.
 template <int S, int NWAVE, int CPL, int RPL, bool SEP>
 __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
 {
@@ -551,8 +553,8 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
     const int lane = tid & 63, wv = tid >> 6;
 
     // This thread's staging slots: window group idx = tid + NT*it at (row r,
-    // group g), global offset r * Wp4 + g from the window origin.
-    // (as byte offsets: below 2^32 since WY * Wp4 * 16 is)
+    // group g), byte offset (r * Wp4 + g) * 16 from the window origin (below
+    // 2^32: WY * Wp4 * 16 is).
     uint32_t soff[NLD];
 #pragma unroll
     for (int it = 0; it < NLD; ++it) {
