@@ -70,7 +70,12 @@ extern "C" {
 #define TNO_QTILE 64
 
 /* tno_config.flags */
-#define TNO_CFG_GRAPHS 1u           /* replay kernel sequences as HIP graphs (reserved) */
+#define TNO_CFG_GRAPHS 1u           /* run each request's kernels and device copies as one HIP
+                                       graph: captured at submit, used to update an executable
+                                       graph of the same structure left by an earlier request
+                                       (instantiated the first time), then launched; the phase
+                                       times of tno_result are 0 in this mode.  Needs an own
+                                       stream pool or a non-default stream. */
 #define TNO_CFG_AUTOTUNE 2u         /* time the search's tile shapes and trajectory blocks on the
                                        first request of each shape class; keep the fastest */
 

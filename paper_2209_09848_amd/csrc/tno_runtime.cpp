@@ -421,6 +421,8 @@ struct Request {
     hipEvent_t ev[6] = {};   // phase boundaries; ev[0] start, ev[5] end
     std::chrono::steady_clock::time_point t_submit;
     uint64_t updates = 0;
+    hipGraphExec_t exec = nullptr;   // graph mode: the executable graph this request ran
+    std::string exec_key;
 };
 
 // Device arenas of finished requests, kept for reuse: a later request takes
@@ -482,6 +484,9 @@ struct tno_search {
         double rate;
     };
     bool autotune = false;
+    bool graphs = false;
+    // executable graphs not in flight, by request structure (graph_key)
+    std::multimap<std::string, hipGraphExec_t> free_execs;
     std::string arch;
     std::string tune_path;
     std::map<std::string, Tuned> tuned;
@@ -645,8 +650,28 @@ tno::SearchArgs search_args(const Request *q, float *snr, float *flux, int nfram
 float *snr_map(Request *q) { return q->plan.own_snr ? at<float>(q->arena, q->plan.o_snr) : q->out.snr; }
 float *flux_map(Request *q) { return q->plan.own_flux ? at<float>(q->arena, q->plan.o_flux) : q->out.flux; }
 
-// Enqueue everything before the numerator search: weighting, table, trail, Lam.
-hipError_t enqueue_front(Request *q, const tno_request *r)
+// Enqueue what precedes the kernels: the wait on a resident stack's upload,
+// the start event, and the host-side trail layout and search order.  (Kept
+// out of a captured graph: host-to-device copies and cross-stream waits.)
+hipError_t enqueue_pre(Request *q)
+{
+    const Plan &p = q->plan;
+    hipStream_t st = q->stream;
+    void *A = q->arena;
+    hipError_t e;
+    if (q->stack && q->stack->ready)
+        TRY(hipStreamWaitEvent(st, q->stack->ready, 0));
+    TRY(hipEventRecord(q->ev[0], st));
+    TRY(hipMemcpyAsync(at<void>(A, p.o_trail), p.trail.data(), p.trail.size() * sizeof(tno::TrailInfo),
+                       hipMemcpyHostToDevice, st));
+    TRY(hipMemcpyAsync(at<void>(A, p.o_perm), p.perm.data(), p.perm.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, st));
+    return hipSuccess;
+}
+
+// Enqueue the kernels before the numerator search: weighting, table, trail,
+// Lam; `events`: record the phase boundaries (not inside a captured graph).
+hipError_t enqueue_front(Request *q, const tno_request *r, bool events)
 {
     const Plan &p = q->plan;
     hipStream_t st = q->stream;
@@ -654,26 +679,21 @@ hipError_t enqueue_front(Request *q, const tno_request *r)
     const Inputs in = inputs_of(q, r);
     const int HW = p.H * p.W;
     hipError_t e;
-    if (q->stack && q->stack->ready)
-        TRY(hipStreamWaitEvent(st, q->stack->ready, 0));
-    TRY(hipEventRecord(q->ev[0], st));
     TRY(tno::launch_zero(st, at<int32_t>(A, p.o_err), 1));
-    TRY(hipMemcpyAsync(at<void>(A, p.o_trail), p.trail.data(), p.trail.size() * sizeof(tno::TrailInfo),
-                       hipMemcpyHostToDevice, st));
-    TRY(hipMemcpyAsync(at<void>(A, p.o_perm), p.perm.data(), p.perm.size() * sizeof(int32_t),
-                       hipMemcpyHostToDevice, st));
     TRY(tno::launch_ivar(st, HW, in.sigma, at<float>(A, p.o_iv32), at<double>(A, p.o_iv64),
                          at<int32_t>(A, p.o_err)));
     TRY(tno::launch_prep_z(st, p.dtype, in.R, in.scales, at<float>(A, p.o_iv32), at<float4>(A, p.o_Z),
                            p.T, p.H, p.W, p.Hp, p.Wp4, p.Pt, p.Pl));
-    TRY(hipEventRecord(q->ev[1], st));
+    if (events)
+        TRY(hipEventRecord(q->ev[1], st));
     const tno::PrfSpec prf{p.kind, p.S, p.sigma_px, in.prf_tab, p.table_q};
     TRY(tno::launch_table(st, p.J, p.T, in.times, p.t_ref, in.vel, in.jit, prf,
                           at<int32_t>(A, p.o_tab32), at<double>(A, p.o_tab64)));
     TRY(tno::launch_trail(st, p.J, p.T, p.S, p.sep, at<int32_t>(A, p.o_tab32), at<double>(A, p.o_tab64),
                           at<tno::TrailInfo>(A, p.o_trail), at<int2>(A, p.o_colmeta),
                           at<double>(A, p.o_kvals), at<int32_t>(A, p.o_err)));
-    TRY(hipEventRecord(q->ev[2], st));
+    if (events)
+        TRY(hipEventRecord(q->ev[2], st));
     tno::LambdaArgs la;
     la.info = at<tno::TrailInfo>(A, p.o_trail);
     la.colmeta = at<int2>(A, p.o_colmeta);
@@ -687,12 +707,14 @@ hipError_t enqueue_front(Request *q, const tno_request *r)
     la.nty = p.lnty;
     la.n_items = p.lntx * p.lnty * p.J;
     TRY(tno::launch_lambda(st, la));
-    TRY(hipEventRecord(q->ev[3], st));
+    if (events)
+        TRY(hipEventRecord(q->ev[3], st));
     return hipSuccess;
 }
 
-// Enqueue the numerator search, the reductions and the output copies.
-hipError_t enqueue_back(Request *q)
+// Enqueue the numerator search, the reductions and the output copies;
+// `events`: record the phase boundaries and the end event.
+hipError_t enqueue_back(Request *q, bool events)
 {
     const Plan &p = q->plan;
     hipStream_t st = q->stream;
@@ -703,7 +725,8 @@ hipError_t enqueue_back(Request *q)
     hipError_t e;
     const tno::SearchArgs sa = search_args(q, snr, flux, p.T);
     TRY(tno::launch_search(st, p.S, p.sep, p.variant, sa));
-    TRY(hipEventRecord(q->ev[4], st));
+    if (events)
+        TRY(hipEventRecord(q->ev[4], st));
     TRY(tno::launch_trajmax(st, p.J, p.ntiles, p.W, HW, sa.tile_keys, snr, flux, at<void>(A, p.o_tmax)));
     TRY(tno::launch_best(st, p.J, HW, snr, at<float>(A, p.o_best), at<int32_t>(A, p.o_bestj)));
     if (p.k > 0)
@@ -737,7 +760,8 @@ hipError_t enqueue_back(Request *q)
         if (o.best_traj)
             TRY(hipMemcpyAsync(o.best_traj, at<void>(A, p.o_bestj), (size_t)HW * 4, hipMemcpyDeviceToDevice, st));
     }
-    TRY(hipEventRecord(q->ev[5], st));
+    if (events)
+        TRY(hipEventRecord(q->ev[5], st));
     return hipSuccess;
 }
 
@@ -808,10 +832,79 @@ hipError_t autotune(tno_search *h, Request *q)
     h->save_tuning();
     return hipSuccess;
 }
+
+// Everything that fixes the node structure of a request's graph: sizes,
+// kernel shapes and which optional kernels and copies run.  Pointers and
+// scalar arguments are free (an executable graph is updated to them).
+std::string graph_key(const Request *q)
+{
+    const Plan &p = q->plan;
+    const tno_outputs &o = q->out;
+    const unsigned copies = p.dev ? ((o.significance && p.box > 0) << 0 | (o.detections && p.kdet > 0) << 1 |
+                                     (o.traj_max != nullptr) << 2 | (o.topk && p.k > 0) << 3 |
+                                     (o.best_snr != nullptr) << 4 | (o.best_traj != nullptr) << 5)
+                                  : 0u;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %u", p.H, p.W, p.T,
+             p.J, p.S, (int)p.sep, p.kind, p.variant, p.tblock, p.dtype, p.k, p.box, p.kdet,
+             (int)p.own_snr, (int)p.own_flux, (int)p.dev, (int)p.jitter, p.Hp, p.Wp4, p.lntx, p.lnty,
+             copies);
+    return buf;
+}
+
+// Graph mode: the request's kernels and device copies are captured into a
+// graph, which updates an executable graph of the same structure left by an
+// earlier request (or is instantiated), and launched.  Uploads, the wait on a
+// resident stack and the start/end events stay outside the graph; phase
+// times are not recorded.
+hipError_t run_graphed(tno_search *h, Request *q, const tno_request *req)
+{
+    hipError_t e = enqueue_pre(q);
+    if (e != hipSuccess)
+        return e;
+    if ((e = hipStreamBeginCapture(q->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return e;
+    hipError_t ek = enqueue_front(q, req, false);
+    if (ek == hipSuccess)
+        ek = enqueue_back(q, false);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(q->stream, &g);
+    if (ek != hipSuccess || e != hipSuccess) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return ek != hipSuccess ? ek : e;
+    }
+    const std::string key = graph_key(q);
+    hipGraphExec_t x = nullptr;
+    auto it = h->free_execs.find(key);
+    if (it != h->free_execs.end()) {
+        x = it->second;
+        h->free_execs.erase(it);
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult ur = hipGraphExecUpdateSuccess;
+        if (hipGraphExecUpdate(x, g, &bad, &ur) != hipSuccess || ur != hipGraphExecUpdateSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(x);
+            x = nullptr;
+        }
+    }
+    if (!x)
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess)
+        return e;
+    q->exec = x;
+    q->exec_key = key;
+    if ((e = hipGraphLaunch(x, q->stream)) != hipSuccess)
+        return e;
+    return hipEventRecord(q->ev[5], q->stream);
+}
 #undef TRY
 
 void release(tno_search *hd, Request *q)
 {
+    if (q->exec)
+        hd->free_execs.emplace(q->exec_key, q->exec);
     if (q->arena) {
         hd->cache.put(q->arena, q->arena_bytes);
         hd->in_use -= q->plan.bytes;
@@ -947,6 +1040,7 @@ int tno_search_create(const tno_config *cfg, tno_search **out_handle)
     }
     h->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
     h->autotune = (cfg->flags & TNO_CFG_AUTOTUNE) != 0;
+    h->graphs = (cfg->flags & TNO_CFG_GRAPHS) != 0;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, cfg->device) == hipSuccess) {
         h->arch = prop.gcnArchName;
@@ -1155,8 +1249,12 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
         else
             tune_now = h->autotune;
     }
-    if ((e = enqueue_front(q, req)) != hipSuccess || (tune_now && (e = autotune(h, q)) != hipSuccess) ||
-        (e = enqueue_back(q)) != hipSuccess) {
+    if (h->graphs && !tune_now)
+        e = run_graphed(h, q, req);
+    else if ((e = enqueue_pre(q)) == hipSuccess && (e = enqueue_front(q, req, true)) == hipSuccess &&
+             (!tune_now || (e = autotune(h, q)) == hipSuccess))
+        e = enqueue_back(q, true);
+    if (e != hipSuccess) {
         (void)hipStreamSynchronize(q->stream);
         release(h, q);
         return hip_fail(e, "enqueue", nullptr, 0);
@@ -1195,7 +1293,7 @@ int tno_search_poll(tno_search *h, uint64_t ticket, int32_t timeout_ms, tno_resu
                 if (hipEventElapsedTime(&ms, q->ev[0], q->ev[5]) == hipSuccess)
                     res.device_ms = ms;
                 double *ph[5] = {&res.prep_ms, &res.table_ms, &res.lambda_ms, &res.search_ms, &res.reduce_ms};
-                for (int i = 0; i < 5; ++i)
+                for (int i = 0; i < 5 && !q->exec; ++i)      // (graph mode records no phases)
                     if (hipEventElapsedTime(&ms, q->ev[i], q->ev[i + 1]) == hipSuccess)
                         *ph[i] = ms;
                 int32_t err = 0, counts[4] = {0, 0, 0, 0};
@@ -1274,6 +1372,9 @@ void tno_search_destroy(tno_search *h)
         for (auto &kv : h->live)
             release(h, kv.second);
         h->live.clear();
+        for (auto &kv : h->free_execs)
+            (void)hipGraphExecDestroy(kv.second);
+        h->free_execs.clear();
         for (auto &kv : h->stacks) {
             h->cache.put(kv.second->block, kv.second->block_bytes);
             if (kv.second->ready)

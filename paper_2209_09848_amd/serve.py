@@ -117,7 +117,7 @@ class StackPool:
 
 
 def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=16,
-               max_inflight=8, log=None):
+               max_inflight=8, log=None, graphs=False):
     """Serve `specs` in arrival order.  Returns per-request records."""
     import torch
     pool = StackPool({s.key: (s.side, s.frames) for s in specs}, dtype, device)
@@ -129,7 +129,7 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
     pending = collections.deque(sorted(specs, key=lambda s: s.arrival))
     inflight = {}
     h = tno.Search(0, own_streams=True, max_inflight=max_inflight,
-                   hbm_budget_bytes=int(budget_gb * 1e9))
+                   hbm_budget_bytes=int(budget_gb * 1e9), graphs=graphs)
     t0 = time.perf_counter()
     try:
         while pending or queue or inflight:
@@ -209,6 +209,8 @@ def main(argv=None):
     ap.add_argument("--max-side", type=int, default=2048)
     ap.add_argument("--dtypes", default="f32,bf16")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--modes", default="eager,graphs",
+                    help="eager launches and/or requests run as HIP graphs")
     args = ap.parse_args(argv)
 
     def log(m):
@@ -227,12 +229,15 @@ def main(argv=None):
     log("mean device time %.1f ms -> arrival rate %.2f req/s" % (mean_s * 1e3, rate))
     out = {"load": args.load, "arrival_rate_per_s": rate, "forms": {}}
     for dt in args.dtypes.split(","):
-        sp = poisson_arrivals([Spec(s.key, s.side, s.frames, s.traj_idx) for s in specs], rate,
-                              args.seed)
-        log("serving %d requests, dtype %s" % (len(sp), dt))
-        recs = run_stream(sp, bank, dtype=dt, budget_gb=args.budget_gb, log=None)
-        out["forms"][dt] = summarize(recs, args.warm)
-        log("%s: %s" % (dt, json.dumps(out["forms"][dt])))
+        for mode in args.modes.split(","):
+            sp = poisson_arrivals([Spec(s.key, s.side, s.frames, s.traj_idx) for s in specs], rate,
+                                  args.seed)
+            name = dt if mode == "eager" else dt + "+graphs"
+            log("serving %d requests, %s" % (len(sp), name))
+            recs = run_stream(sp, bank, dtype=dt, budget_gb=args.budget_gb, log=None,
+                              graphs=mode == "graphs")
+            out["forms"][name] = summarize(recs, args.warm)
+            log("%s: %s" % (name, json.dumps(out["forms"][name])))
     print(json.dumps(out), flush=True)
 
 

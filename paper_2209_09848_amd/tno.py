@@ -246,7 +246,7 @@ class Search:
 
     def __init__(self, device: int = 0, max_inflight: int = 64, hbm_budget_bytes: int = 0,
                  stream=None, own_streams: bool = False, autotune: bool = False,
-                 tune_cache_path: str | None = None):
+                 tune_cache_path: str | None = None, graphs: bool = False):
         """own_streams=True: the library runs requests on its own pool of streams
         (concurrent requests overlap; inputs must be complete before submit);
         otherwise every request runs on `stream` (default: torch's current)."""
@@ -259,7 +259,7 @@ class Search:
         cfg.device = device
         cfg.max_inflight = max_inflight
         cfg.hbm_budget_bytes = hbm_budget_bytes
-        cfg.flags = TNO_CFG_AUTOTUNE if autotune else 0
+        cfg.flags = (TNO_CFG_AUTOTUNE if autotune else 0) | (TNO_CFG_GRAPHS if graphs else 0)
         cfg.reserved = 0
         cfg.stream = ctypes.c_void_p(stream) if stream else None
         self._path = tune_cache_path.encode() if tune_cache_path else None

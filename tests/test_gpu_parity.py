@@ -307,6 +307,43 @@ def test_ffi_full_size_sampled_parity():
 
 # ------------------------------------------------------------------ serving: residency, streams
 
+def test_graph_mode_replays_match_eager():
+    """TNO_CFG_GRAPHS: each request is captured as a graph that updates the
+    cached executable graph of its structure.  Every replay gives the eager
+    request's bits, with other GPU work and synchronisations in between and
+    fresh output buffers each time; a second shape gets its own graph; two
+    requests of one structure in flight at once each get an executable."""
+    R, sigma, times, vel = _rand_problem(60, 12, 50, 170, 4)
+    R2, sigma2, times2, vel2 = _rand_problem(61, 9, 37, 133, 3)
+    ref, _ = run_gpu(R, sigma, times, vel, float(times[0]), top_k=10)
+    ref2, _ = run_gpu(R2, sigma2, times2, vel2, float(times2[0]), top_k=10)
+
+    def same(g, r):
+        return (np.array_equal(g["snr"], r["snr"]) and np.array_equal(g["flux"], r["flux"])
+                and np.array_equal(g["best_traj"], r["best_traj"]) and g["topk"] == r["topk"])
+
+    with tno.Search(0, own_streams=True, graphs=True) as h:
+        for rep in range(4):
+            print("graph replay", rep, flush=True)
+            g, res = run_gpu(R, sigma, times, vel, float(times[0]), top_k=10, handle=h)
+            assert same(g, ref) and res.search_ms == 0.0 and res.device_ms > 0.0
+            x = torch.randn((512, 512), device=DEV)
+            float((x @ x).sum())
+            torch.cuda.synchronize()
+            g2, _ = run_gpu(R2, sigma2, times2, vel2, float(times2[0]), top_k=10, handle=h)
+            assert same(g2, ref2)
+        # two requests of the same structure in flight together
+        Rt, st_, tt, vt = _to(R), _to(sigma), _to(times), _to(vel)
+        outs = [tno.alloc_outputs(vel.shape[0], R.shape[1], R.shape[2], 10, device=DEV) for _ in range(2)]
+        reqs = [tno.make_request(Rt, st_, tt, vt, t_ref=float(times[0]), top_k=10) for _ in range(2)]
+        torch.cuda.synchronize()
+        tickets = [h.submit(r, o[1]) for r, o in zip(reqs, outs)]
+        for t in tickets:
+            h.wait(t)
+        for o, _ in outs:
+            assert np.array_equal(o["snr"].cpu().numpy(), ref["snr"])
+
+
 def test_resident_stack_reuse_and_key_errors():
     R, sigma, times, vel = _rand_problem(50, 10, 40, 150, 3)
     ref, _ = run_gpu(R, sigma, times, vel, float(times[0]), top_k=8)
