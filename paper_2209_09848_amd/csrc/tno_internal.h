@@ -26,7 +26,7 @@ __host__ __device__ constexpr int search_tx(int v) { return 64 * SEARCH_VARIANTS
 __host__ __device__ constexpr int search_ty(int v) { return SEARCH_VARIANTS[v].rpl * SEARCH_VARIANTS[v].nwave; }
 // Normaliser tile: 64 columns (1 per lane) x 32 rows (8 per lane, 4 waves).
 constexpr int LAMBDA_TX = 64;
-constexpr int LAMBDA_TY = 32;
+constexpr int LAMBDA_TY = 64;
 // Frames summed in FP32 before each FP64 accumulation of the numerator.
 constexpr int FRAME_CHUNK = 8;
 

@@ -29,6 +29,7 @@ namespace tno {
 // ------------------------------------------------------------------ helpers
 
 typedef __attribute__((address_space(4))) int32_t cint32_t;   // constant address space
+typedef __attribute__((address_space(3))) float lfloat_t;      // LDS
 // Word 3 of a raw (unformatted, stride 0) buffer resource on gfx9-family GPUs.
 constexpr int BUF_DWORD3 = 0x00020000;
 
@@ -425,15 +426,16 @@ hipError_t launch_trail(hipStream_t st, int J, int T, int S, bool sep, const int
 // ------------------------------------------------------------------ k_lambda (FP64)
 
 // Lam_j(y, x) = sum over trail columns qx, rows qy of K_j(qy, qx) ivar(y+qy, x+qx).
-// A lane owns one image column x and 8 consecutive rows.  Each trail column's
+// A lane owns one image column x and 16 consecutive rows.  Each trail column's
 // run is zero-padded to whole chunks of 8 values; per chunk the 8 K values are
-// wave-uniform (one scalar load) and a sliding window of 15 ivar values down
-// the image column feeds 64 branch-free FP64 FMAs, each ivar load serving up
-// to 8 outputs.
+// wave-uniform (scalar loads) and a sliding window of 23 ivar values down the
+// image column feeds 128 branch-free FP64 FMAs, each ivar load serving up to
+// 16 outputs (the kernel is bound by those loads: 8 rows per lane ran 1.2x
+// slower, 32 rows only 3-5% faster at 160 VGPRs).
 __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
 {
-    constexpr int R = 8;    // outputs per lane
-    constexpr int C = 8;    // K values per chunk
+    constexpr int R = LAMBDA_TY / 4;   // outputs per lane (4 waves stacked)
+    constexpr int C = 8;               // K values per chunk
     int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.n_items)
         return;
@@ -663,8 +665,26 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
             // v[1], v[3], .. from the other half starting at (s+1)/2
             // (odd CPL: column s + t sits at half (s+t)&1, index (s+t)>>1)
             const int par = d_cur & 1;
-            const float *pa = wrow + par * HALF + (d_cur >> 1) + (CPL / 2) * lane;
-            const float *pb = wrow + (1 - par) * HALF + ((d_cur + 1) >> 1) + (CPL / 2) * lane;
+            // SPLIT: LDS byte addresses of the two runs, one base per group of
+            // RG window rows, so that every read of a group is an immediate
+            // offset of its base (paired reads reach 255 words): the bases are
+            // made opaque to keep the compiler from re-deriving one per row
+            constexpr int NR = RPL + S - 1;
+            constexpr int RG = (255 - (NV - 1) / 2) / LH + 1;
+            constexpr int NGR = (NR + RG - 1) / RG;
+            uint32_t ga[NGR], gb[NGR];
+            if constexpr (SPLIT) {
+                const uint32_t a0 = (uint32_t)(uintptr_t)(const lfloat_t *)(wrow + par * HALF + (d_cur >> 1) +
+                                                                           (CPL / 2) * lane);
+                const uint32_t b0 = (uint32_t)(uintptr_t)(const lfloat_t *)(wrow + (1 - par) * HALF +
+                                                                           ((d_cur + 1) >> 1) + (CPL / 2) * lane);
+#pragma unroll
+                for (int g = 0; g < NGR; ++g) {
+                    ga[g] = a0 + (uint32_t)(g * RG * LH * 4);
+                    gb[g] = b0 + (uint32_t)(g * RG * LH * 4);
+                    asm volatile("" : "+v"(ga[g]), "+v"(gb[g]));
+                }
+            }
             const float *pt[SPLIT ? 1 : NV];
             if constexpr (!SPLIT) {
                 const int s0 = d_cur + CPL * lane;
@@ -675,10 +695,13 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
             auto row = [&](int rr, float (&v)[NV]) {
 #pragma unroll
                 for (int t = 0; t < NV; ++t) {
-                    if constexpr (SPLIT)
-                        v[t] = (t & 1) ? pb[rr * LH + (t >> 1)] : pa[rr * LH + (t >> 1)];
-                    else
+                    if constexpr (SPLIT) {
+                        const int g = rr / RG, rl = rr - g * RG;
+                        const lfloat_t *q = (const lfloat_t *)(uintptr_t)((t & 1) ? gb[g] : ga[g]);
+                        v[t] = q[rl * LH + (t >> 1)];
+                    } else {
                         v[t] = pt[t][rr * LH];
+                    }
                 }
             };
             // window rows are read one row ahead of their use (the loop is
