@@ -521,7 +521,7 @@ hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a)
 // S x S stamp.  The table entry (shift, weights) is wave-uniform (scalar
 // loads).  Frame partials accumulate in FP32 over FRAME_CHUNK frames, then
 // into FP64.
-template <int S, int NWAVE, int CPL, int RPL, bool SEP>
+template <int S, int NWAVE, int CPL, int RPL, bool SEP, bool XCH>
 __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
 {
     constexpr int h = S / 2;
@@ -535,7 +535,13 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
     constexpr int TS = table_stride(S, SEP);
     constexpr int NW = table64_stride(S, SEP);   // FP32 weights per table entry
     constexpr int NV = CPL + S - 1;
-    __shared__ __align__(16) float win[2][NWIN * 4];
+    // XCH: one window buffer plus the exchange rows of the horizontal pass
+    // ((NWAVE+1) x (S-1) rows of TX values); otherwise two window buffers
+    static_assert(!XCH || (SEP && CPL % 2 == 0 && S > 1 && S - 1 <= RPL),
+                  "the exchange form needs a separable stamp wider than 1, even CPL and S-1 <= RPL");
+    constexpr int NXR = XCH ? (NWAVE + 1) * (S - 1) : 0;
+    __shared__ __align__(16) float win[XCH ? 1 : 2][NWIN * 4];
+    __shared__ __align__(16) float xch[XCH ? NXR * TX : 1];
 
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.n_items)
@@ -648,7 +654,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
     for (int k0 = 0; k0 < a.nframes; k0 += FRAME_CHUNK) {
         const int k1 = min(k0 + FRAME_CHUNK, a.nframes);
         for (int k = k0; k < k1; ++k) {
-            const int buf = k & 1;
+            const int buf = XCH ? 0 : (k & 1);
             // the last iteration re-fetches frame T-1 into the idle buffer: no
             // branch around the prefetch, so its store stays behind the arithmetic
             const int d_next = fetch(min(k + 1, a.nframes - 1), pre);
@@ -673,11 +679,11 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
             constexpr int RG = (255 - (NV - 1) / 2) / LH + 1;
             constexpr int NGR = (NR + RG - 1) / RG;
             uint32_t ga[NGR], gb[NGR];
+            uint32_t a0 = 0, b0 = 0;
             if constexpr (SPLIT) {
-                const uint32_t a0 = (uint32_t)(uintptr_t)(const lfloat_t *)(wrow + par * HALF + (d_cur >> 1) +
-                                                                           (CPL / 2) * lane);
-                const uint32_t b0 = (uint32_t)(uintptr_t)(const lfloat_t *)(wrow + (1 - par) * HALF +
-                                                                           ((d_cur + 1) >> 1) + (CPL / 2) * lane);
+                a0 = (uint32_t)(uintptr_t)(const lfloat_t *)(wrow + par * HALF + (d_cur >> 1) + (CPL / 2) * lane);
+                b0 = (uint32_t)(uintptr_t)(const lfloat_t *)(wrow + (1 - par) * HALF + ((d_cur + 1) >> 1) +
+                                                             (CPL / 2) * lane);
 #pragma unroll
                 for (int g = 0; g < NGR; ++g) {
                     ga[g] = a0 + (uint32_t)(g * RG * LH * 4);
@@ -704,6 +710,102 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
                     }
                 }
             };
+            // horizontal pass of one window row (separable stamp)
+            auto horiz = [&](const float (&v)[NV], float (&hs)[CPL]) {
+                if constexpr (SEP) {
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        float sum = wt[S] * v[c];
+#pragma unroll
+                        for (int b = 1; b < S; ++b)
+                            sum = fmaf(wt[S + b], v[c + b], sum);
+                        hs[c] = sum;
+                    }
+                }
+            };
+            // vertical pass: horizontal row rr (relative to the wave's first
+            // row) is stamp row aa of output row rr - aa
+            auto vert = [&](int rr, const float (&hs)[CPL]) {
+#pragma unroll
+                for (int aa = 0; aa < S; ++aa) {
+                    const int o = rr - aa;
+                    if (o >= 0 && o < RPL) {
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c)
+                            part[o][c] = fmaf(wt[aa], hs[c], part[o][c]);
+                    }
+                }
+            };
+            if constexpr (XCH) {
+                // Each horizontal row is computed once per block: wave v does
+                // its RPL own rows and leaves the first S-1 of them in xch rows
+                // v(S-1) ... for the wave above (wave 0's copy is not read);
+                // the S-1 rows below the tile are spread over the waves and
+                // land in xch rows NWAVE(S-1) ...; wave w then reads its halo
+                // rows from xch rows (w+1)(S-1) ...  One window buffer: it is
+                // refilled between the two barriers, after every wave has
+                // read it.
+                const int wvu = __builtin_amdgcn_readfirstlane(wv);
+                auto put = [&](int xrow, const float (&hs)[CPL]) {
+                    float *xr = xch + xrow * TX + CPL * lane;
+#pragma unroll
+                    for (int c = 0; c < CPL; c += 2)
+                        *reinterpret_cast<float2 *>(xr + c) = make_float2(hs[c], hs[c + 1]);
+                };
+                float vbuf[2][NV];
+                row(0, vbuf[0]);
+#pragma unroll
+                for (int rr = 0; rr < RPL; ++rr) {
+                    if (rr + 1 < RPL)
+                        row(rr + 1, vbuf[(rr + 1) & 1]);
+                    float hs[CPL];
+                    horiz(vbuf[rr & 1], hs);
+                    vert(rr, hs);
+                    if (rr < S - 1)
+                        put(wvu * (S - 1) + rr, hs);
+                }
+                constexpr int NB = (S - 1 + NWAVE - 1) / NWAVE;   // rows below the tile per wave
+#pragma unroll
+                for (int m = 0; m < NB; ++m) {
+                    const int i = wvu + m * NWAVE;
+                    if ((S - 1) % NWAVE == 0 || i < S - 1) {
+                        const uint32_t off = (uint32_t)((TY + i - wvu * RPL) * LH * 4);
+                        const lfloat_t *qa = (const lfloat_t *)(uintptr_t)(a0 + off);
+                        const lfloat_t *qb = (const lfloat_t *)(uintptr_t)(b0 + off);
+                        float v[NV];
+#pragma unroll
+                        for (int t = 0; t < NV; ++t)
+                            v[t] = (t & 1) ? qb[t >> 1] : qa[t >> 1];
+                        float hs[CPL];
+                        horiz(v, hs);
+                        put(NWAVE * (S - 1) + i, hs);
+                    }
+                }
+                // keep the own-row arithmetic ahead of the barrier
+#pragma unroll
+                for (int o = 0; o < RPL; ++o)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c)
+                        asm volatile("" : "+v"(part[o][c]));
+                __builtin_amdgcn_sched_barrier(0);
+                __syncthreads();
+                store(0, pre);
+#pragma unroll
+                for (int i = 0; i < S - 1; ++i) {
+                    const float *xr = xch + ((wvu + 1) * (S - 1) + i) * TX + CPL * lane;
+                    float hs[CPL];
+#pragma unroll
+                    for (int c = 0; c < CPL; c += 2) {
+                        const float2 q = *reinterpret_cast<const float2 *>(xr + c);
+                        hs[c] = q.x;
+                        hs[c + 1] = q.y;
+                    }
+                    vert(RPL + i, hs);
+                }
+                __syncthreads();
+                d_cur = d_next;
+                continue;
+            }
             // window rows are read one row ahead of their use (the loop is
             // unrolled, so the two buffers are register renames)
             float vbuf[2][NV];
@@ -716,23 +818,8 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
                 if constexpr (SEP) {
                     // horizontal pass of the row, streamed into the vertical pass
                     float hs[CPL];
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) {
-                        float sum = wt[S] * v[c];
-#pragma unroll
-                        for (int b = 1; b < S; ++b)
-                            sum = fmaf(wt[S + b], v[c + b], sum);
-                        hs[c] = sum;
-                    }
-#pragma unroll
-                    for (int aa = 0; aa < S; ++aa) {
-                        const int o = rr - aa;
-                        if (o >= 0 && o < RPL) {
-#pragma unroll
-                            for (int c = 0; c < CPL; ++c)
-                                part[o][c] = fmaf(wt[aa], hs[c], part[o][c]);
-                        }
-                    }
+                    horiz(v, hs);
+                    vert(rr, hs);
                 } else {
                     // general stamp: window row rr is stamp row aa of output row rr - aa
 #pragma unroll
@@ -825,7 +912,9 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
 template <int S, int NWAVE, int CPL, int RPL = 8, bool SEP = true>
 static void launch_search_t(hipStream_t st, const SearchArgs &a)
 {
-    hipLaunchKernelGGL((k_search<S, NWAVE, CPL, RPL, SEP>), dim3(xcd_grid(a.n_items)),
+    // the shared-row form wherever it applies
+    constexpr bool XCH = SEP && CPL % 2 == 0 && S > 1 && S - 1 <= RPL && NWAVE > 1;
+    hipLaunchKernelGGL((k_search<S, NWAVE, CPL, RPL, SEP, XCH>), dim3(xcd_grid(a.n_items)),
                        dim3(64 * NWAVE), 0, st, a);
 }
 
