@@ -24,11 +24,12 @@ constexpr int SEARCH_MAX_TX = 256;
 constexpr int SEARCH_MAX_TY = 64;
 __host__ __device__ constexpr int search_tx(int v) { return 64 * SEARCH_VARIANTS[v].cpl; }
 __host__ __device__ constexpr int search_ty(int v) { return SEARCH_VARIANTS[v].rpl * SEARCH_VARIANTS[v].nwave; }
-// Normaliser tile: 64 columns (1 per lane) x 32 rows (8 per lane, 4 waves).
+// Normaliser tile: 64 columns (1 per lane) x 64 rows (16 per lane, 4 waves).
 constexpr int LAMBDA_TX = 64;
 constexpr int LAMBDA_TY = 64;
 // Frames summed in FP32 before each FP64 accumulation of the numerator.
 constexpr int FRAME_CHUNK = 8;
+constexpr int LDS_PER_CU = 160 * 1024;   // gfx950 LDS bytes per compute unit
 
 // Dwords per offset/weight table entry, padded to 16 bytes: iy, ix and the
 // FP32 weights, gy[S], gx[S] for a separable (Gaussian) PRF or W[S][S]

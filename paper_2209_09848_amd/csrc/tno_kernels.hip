@@ -514,13 +514,17 @@ hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a)
 // (TX+S-1) columns, fetched as aligned float4 groups (buffer loads, the
 // sub-float4 offset d applied when reading) and staged de-interleaved into
 // LDS.  The window of frame k+1 is fetched into registers before frame k is
-// computed and stored into the other half of a double-buffered LDS window
-// afterwards, so global latency overlaps the arithmetic and one barrier per
-// frame suffices.  SEP: the separable stamp, a horizontal pass of S taps per
+// computed and stored into LDS afterwards, so global latency overlaps the
+// arithmetic.  SEP: the separable stamp, a horizontal pass of S taps per
 // window row streamed into a vertical pass of S taps; otherwise the general
-// S x S stamp.  The table entry (shift, weights) is wave-uniform (scalar
-// loads).  Frame partials accumulate in FP32 over FRAME_CHUNK frames, then
-// into FP64.
+// S x S stamp.  XCH (separable stamps): every horizontal row is computed once
+// per block and the S-1 halo rows below each wave's strip come from the wave
+// that owns them through a small LDS exchange buffer; the window is single
+// buffered and refilled between two barriers per frame.  Otherwise each wave
+// computes its own halo rows and a double-buffered window needs one barrier
+// per frame.  The table entry (shift, weights) is wave-uniform (scalar loads).
+// Frame partials accumulate in FP32 over FRAME_CHUNK frames, then into FP64;
+// every form adds the terms of an output in the same order.
 template <int S, int NWAVE, int CPL, int RPL, bool SEP, bool XCH>
 __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
 {
@@ -541,7 +545,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
                   "the exchange form needs a separable stamp wider than 1, even CPL and S-1 <= RPL");
     constexpr int NXR = XCH ? (NWAVE + 1) * (S - 1) : 0;
     __shared__ __align__(16) float win[XCH ? 1 : 2][NWIN * 4];
-    __shared__ __align__(16) float xch[XCH ? NXR * TX : 1];
+    __shared__ __align__(16) float xch[XCH ? 2 * NXR * TX : 1];
 
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.n_items)
@@ -647,6 +651,37 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
             acc[o][c] = 0.0;
         }
 
+    // XCH: the halo rows of frame k are added at the start of frame k+1 (or
+    // at the end of the frame chunk), from the exchange buffer of frame k's
+    // parity and with frame k's vertical weights, in the same order as
+    // without the exchange
+    float wyp[S];
+    auto halo = [&](int kp) {
+        if constexpr (XCH) {
+            const int wvu = __builtin_amdgcn_readfirstlane(wv);
+#pragma unroll
+            for (int i = 0; i < S - 1; ++i) {
+                const float *xr = xch + (kp & 1) * NXR * TX + ((wvu + 1) * (S - 1) + i) * TX + CPL * lane;
+                float hs[CPL];
+#pragma unroll
+                for (int c = 0; c < CPL; c += 2) {
+                    const float2 q = *reinterpret_cast<const float2 *>(xr + c);
+                    hs[c] = q.x;
+                    hs[c + 1] = q.y;
+                }
+#pragma unroll
+                for (int aa = 0; aa < S; ++aa) {
+                    const int o = RPL + i - aa;
+                    if (o >= 0 && o < RPL) {
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c)
+                            part[o][c] = fmaf(wyp[aa], hs[c], part[o][c]);
+                    }
+                }
+            }
+        }
+    };
+
     float4 pre[NLD];
     int d_cur = fetch(0, pre);
     store(0, pre);
@@ -660,6 +695,10 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
             const int d_next = fetch(min(k + 1, a.nframes - 1), pre);
 
             const cint32_t *e = tabj + (size_t)k * TS;
+            if constexpr (XCH) {
+                if (k > k0)
+                    halo(k - 1);
+            }
             float wt[NW];     // gy[S], gx[S] (separable) or W[S][S]
 #pragma unroll
             for (int s = 0; s < NW; ++s)
@@ -742,12 +781,13 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
                 // v(S-1) ... for the wave above (wave 0's copy is not read);
                 // the S-1 rows below the tile are spread over the waves and
                 // land in xch rows NWAVE(S-1) ...; wave w then reads its halo
-                // rows from xch rows (w+1)(S-1) ...  One window buffer: it is
-                // refilled between the two barriers, after every wave has
-                // read it.
+                // rows from xch rows (w+1)(S-1) ... after the frame's second
+                // barrier (two exchange buffers, by frame parity).  One window
+                // buffer: it is refilled between the two barriers, after every
+                // wave has read it.
                 const int wvu = __builtin_amdgcn_readfirstlane(wv);
                 auto put = [&](int xrow, const float (&hs)[CPL]) {
-                    float *xr = xch + xrow * TX + CPL * lane;
+                    float *xr = xch + (k & 1) * NXR * TX + xrow * TX + CPL * lane;
 #pragma unroll
                     for (int c = 0; c < CPL; c += 2)
                         *reinterpret_cast<float2 *>(xr + c) = make_float2(hs[c], hs[c + 1]);
@@ -791,17 +831,8 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
                 __syncthreads();
                 store(0, pre);
 #pragma unroll
-                for (int i = 0; i < S - 1; ++i) {
-                    const float *xr = xch + ((wvu + 1) * (S - 1) + i) * TX + CPL * lane;
-                    float hs[CPL];
-#pragma unroll
-                    for (int c = 0; c < CPL; c += 2) {
-                        const float2 q = *reinterpret_cast<const float2 *>(xr + c);
-                        hs[c] = q.x;
-                        hs[c + 1] = q.y;
-                    }
-                    vert(RPL + i, hs);
-                }
+                for (int aa = 0; aa < S; ++aa)
+                    wyp[aa] = wt[aa];
                 __syncthreads();
                 d_cur = d_next;
                 continue;
@@ -852,6 +883,8 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
             __syncthreads();
             d_cur = d_next;
         }
+        if constexpr (XCH)
+            halo(k1 - 1);
         // frame chunk done: into the FP64 totals
 #pragma unroll
         for (int o = 0; o < RPL; ++o)
@@ -912,8 +945,13 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
 template <int S, int NWAVE, int CPL, int RPL = 8, bool SEP = true>
 static void launch_search_t(hipStream_t st, const SearchArgs &a)
 {
-    // the shared-row form wherever it applies
-    constexpr bool XCH = SEP && CPL % 2 == 0 && S > 1 && S - 1 <= RPL && NWAVE > 1;
+    // the shared-row form wherever it applies and its LDS (one window, two
+    // exchange buffers) keeps as many blocks per CU as two windows do
+    constexpr int NWIN = (RPL * NWAVE + S - 1) * ((64 * CPL + S - 1 + 6) / 4);
+    constexpr int LDS_X = NWIN * 16 + 2 * (NWAVE + 1) * (S - 1) * 64 * CPL * 4;
+    constexpr int LDS_2 = 2 * NWIN * 16;
+    constexpr bool XCH = SEP && CPL % 2 == 0 && S > 1 && S - 1 <= RPL && NWAVE > 1 &&
+                         LDS_PER_CU / LDS_X >= LDS_PER_CU / LDS_2;
     hipLaunchKernelGGL((k_search<S, NWAVE, CPL, RPL, SEP, XCH>), dim3(xcd_grid(a.n_items)),
                        dim3(64 * NWAVE), 0, st, a);
 }
