@@ -78,15 +78,16 @@ struct LambdaArgs {
     const TrailInfo *info;
     const int2 *colmeta;     // per column: (row offset of run start, run length)
     const double *kvals;
-    const double *ivar64;    // [H][W]
+    const double *ivar64;    // [Hq][Wq]: ivar at (Pyt + y, Pxl + x), zero around it
     double *lam;             // [J][H][W]
     int H, W, J, ntx, nty, n_items;
+    int Pyt, Pxl, Wq;
 };
 
 // ---- launch wrappers (all on `st`; return hipError_t of the launch)
 hipError_t launch_zero(hipStream_t st, int32_t *p, int n);
-hipError_t launch_ivar(hipStream_t st, int HW, const float *sigma, float *ivar32, double *ivar64,
-                       int32_t *err);
+hipError_t launch_ivar(hipStream_t st, int H, int W, const float *sigma, float *ivar32, double *ivar64,
+                       int Hq, int Wq, int Pyt, int Pxl, int32_t *err);
 hipError_t launch_prep_z(hipStream_t st, int dtype, const void *R, const float *scales,
                          const float *ivar32, float4 *Z4, int T, int H, int W, int Hp, int Wp4,
                          int Pt, int Pl);

@@ -78,26 +78,36 @@ hipError_t launch_zero(hipStream_t st, int32_t *p, int n)
 
 // ------------------------------------------------------------------ k_ivar
 
-__global__ void k_ivar(int HW, const float *__restrict__ sigma, float *__restrict__ ivar32,
-                       double *__restrict__ ivar64, int32_t *__restrict__ err)
+__global__ void k_ivar(int W, const float *__restrict__ sigma, float *__restrict__ ivar32,
+                       double *__restrict__ ivar64, int64_t HWq, int Wq, int H, int Pyt, int Pxl,
+                       int32_t *__restrict__ err)
 {
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += gridDim.x * blockDim.x) {
-        double s = (double)sigma[p];
-        double iv = (__builtin_isfinite(s) && s > 0.0) ? 1.0 / (s * s) : 0.0;
-        float iv32 = (float)iv;
-        if (!__builtin_isfinite(iv32))
-            atomicOr(err, 2);     // 1/sigma^2 beyond single precision: rejected
-        ivar64[p] = iv;
-        ivar32[p] = iv32;
+    // one thread per element of the zero-bordered FP64 map
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < HWq; q += (int64_t)gridDim.x * blockDim.x) {
+        const int yq = (int)(q / Wq), xq = (int)(q - (int64_t)yq * Wq);
+        const int y = yq - Pyt, x = xq - Pxl;
+        double iv = 0.0;
+        if ((unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W) {
+            const size_t p = (size_t)y * W + x;
+            const double s = (double)sigma[p];
+            iv = (__builtin_isfinite(s) && s > 0.0) ? 1.0 / (s * s) : 0.0;
+            const float iv32 = (float)iv;
+            if (!__builtin_isfinite(iv32))
+                atomicOr(err, 2);     // 1/sigma^2 beyond single precision: rejected
+            ivar32[p] = iv32;
+        }
+        ivar64[q] = iv;
     }
 }
 
-hipError_t launch_ivar(hipStream_t st, int HW, const float *sigma, float *ivar32, double *ivar64,
-                       int32_t *err)
+hipError_t launch_ivar(hipStream_t st, int H, int W, const float *sigma, float *ivar32, double *ivar64,
+                       int Hq, int Wq, int Pyt, int Pxl, int32_t *err)
 {
-    int blocks = (HW + 255) / 256;
+    const int64_t n = (int64_t)Hq * Wq;
+    int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_ivar, dim3(blocks), dim3(256), 0, st, HW, sigma, ivar32, ivar64, err);
+    hipLaunchKernelGGL(k_ivar, dim3((unsigned)blocks), dim3(256), 0, st, W, sigma, ivar32, ivar64, n, Wq, H,
+                       Pyt, Pxl, err);
     return hipGetLastError();
 }
 
@@ -429,9 +439,11 @@ hipError_t launch_trail(hipStream_t st, int J, int T, int S, bool sep, const int
 // A lane owns one image column x and 16 consecutive rows.  Each trail column's
 // run is zero-padded to whole chunks of 8 values; per chunk the 8 K values are
 // wave-uniform (scalar loads) and a sliding window of 23 ivar values down the
-// image column feeds 128 branch-free FP64 FMAs, each ivar load serving up to
-// 16 outputs (the kernel is bound by those loads: 8 rows per lane ran 1.2x
-// slower, 32 rows only 3-5% faster at 160 VGPRs).
+// image column feeds 128 FP64 FMAs, each ivar load serving up to 16 outputs.
+// ivar is read from a copy with a zero border wide enough for every read of
+// the launch, so no load is clamped or masked: a wave's loads of one chunk are
+// buffer loads from a scalar base (the chunk's first row at the wave's first
+// column) with the lane's 8-byte column offset and a scalar row offset.
 __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
 {
     constexpr int R = LAMBDA_TY / 4;   // outputs per lane (4 waves stacked)
@@ -442,10 +454,14 @@ __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
     const int j = item % a.J;
     const int tile = item / a.J;
     const int tyi = tile / a.ntx, txi = tile - tyi * a.ntx;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int x = txi * LAMBDA_TX + lane;
-    const int y0 = tyi * LAMBDA_TY + wv * R;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int xw = txi * LAMBDA_TX;            // the wave's first column
+    const int y0 = tyi * LAMBDA_TY + wv * R;   // the wave's first row
+    const int x = xw + lane;
     const TrailInfo ti = a.info[j];
+    const uint32_t rowb = (uint32_t)a.Wq * 8u;
+    const int voff = lane * 8;
     double acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -455,27 +471,27 @@ __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
         const int len = m.y;
         if (len == 0)
             continue;
-        // branch-free loads: clamp into the image, then zero what lies outside
-        const int X = x + ti.qx0 + c;
-        const bool xin = (unsigned)X < (unsigned)a.W;
-        const double *col = a.ivar64 + min(max(X, 0), a.W - 1);
-        // (multiplying by a 0/1 mask, rather than selecting, keeps the load
-        // unconditional; ivar is finite, so 0 * ivar = 0)
-        auto ld = [&](int Y) -> double {
-            const int Yc = min(max(Y, 0), a.H - 1);
-            const double t = col[(size_t)Yc * a.W];
-            return t * ((xin && Y == Yc) ? 1.0 : 0.0);
+        // the run's first row for this wave, at the wave's first column
+        const double *base = a.ivar64 + (size_t)(a.Pyt + y0 + m.x) * a.Wq + (a.Pxl + xw + ti.qx0 + c);
+        auto ld = [&](const __amdgpu_buffer_rsrc_t &rs, int i) -> double {
+            const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, (int)(i * rowb), 0);
+            return __builtin_bit_cast(double, w);
         };
         const double *kv = a.kvals + ti.val_off + (int64_t)c * ti.cap;
-        const int ybase = y0 + m.x;
         double v[R + C - 1];
+        {
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, 0x7FFFFFFF, BUF_DWORD3);
 #pragma unroll
-        for (int i = 0; i < R - 1; ++i)
-            v[i] = ld(ybase + i);
+            for (int i = 0; i < R - 1; ++i)
+                v[i] = ld(rs, i);
+        }
         for (int q0 = 0; q0 < len; q0 += C) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(base + (size_t)(q0 + R - 1) * a.Wq), (short)0, 0x7FFFFFFF, BUF_DWORD3);
 #pragma unroll
-            for (int i = R - 1; i < R + C - 1; ++i)
-                v[i] = ld(ybase + q0 + i);
+            for (int t = 0; t < C; ++t)
+                v[R - 1 + t] = ld(rs, t);
             double kc[C];
 #pragma unroll
             for (int t = 0; t < C; ++t)

@@ -86,6 +86,7 @@ struct Plan {
     int ntiles_max = 0;               // tiles of the smallest shape (sizes the tile-key buffer)
     std::vector<int32_t> perm;        // velocity-sorted search order
     int lntx = 0, lnty = 0;
+    int lPyt = 0, lPxl = 0, lHq = 0, lWq = 0;   // zero border of the FP64 ivar map
     int64_t N = 0, n_chunks = 0;
     bool own_snr = true, own_flux = true;
     int box = 0, kdet = 0;            // significance window side; detections wanted
@@ -325,6 +326,28 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     p.lnty = (H + tno::LAMBDA_TY - 1) / tno::LAMBDA_TY;
     if ((double)p.lntx * p.lnty * p.J > 2.0e9)
         return fail(TNO_E_INVAL, "too many normaliser work items");
+    {
+        // The normaliser reads ivar at x + qx (x below lntx * TX, qx within a
+        // trail box) and, down a column run [lo, lo + len) of rows inside
+        // [qy_lo, qy_hi], rows y0 + lo ... y0 + lo + round8(len) + R - 2 for a
+        // wave whose first row y0 is at most lnty * TY - R, i.e. at most
+        // lnty * TY + qy_hi + 6.  The border covers all of them.
+        int qxmin = 0, qxmax = 0, qymin = 0, qymax = 0;
+        for (const auto &ti : p.trail) {
+            if (ti.ncols <= 0)
+                continue;
+            qxmin = std::min(qxmin, ti.qx0);
+            qxmax = std::max(qxmax, ti.qx0 + ti.ncols - 1);
+            qymin = std::min(qymin, ti.qy_lo);
+            qymax = std::max(qymax, ti.qy_hi);
+        }
+        p.lPxl = -qxmin;
+        const int pxr = std::max(0, p.lntx * tno::LAMBDA_TX + qxmax - W);
+        p.lPyt = -qymin;
+        const int pyb = std::max(0, p.lnty * tno::LAMBDA_TY + qymax + 7 - H);
+        p.lWq = W + p.lPxl + pxr;
+        p.lHq = H + p.lPyt + pyb;
+    }
     p.N = (int64_t)p.J * H * W;
     p.k = (int)std::min<int64_t>(r->top_k, p.N);
     p.n_chunks = (p.N + tno::TOPK_CHUNK - 1) / tno::TOPK_CHUNK;
@@ -362,7 +385,7 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     }
     p.o_Z = take(T * (size_t)p.Hp * p.Wp4 * 16);
     p.o_iv32 = take(HW * 4);
-    p.o_iv64 = take(HW * 8);
+    p.o_iv64 = take((size_t)p.lHq * p.lWq * 8);
     p.o_tab32 = take(J * T * tno::table_stride(S, p.sep) * 4);
     p.o_tab64 = take(J * T * tno::table64_stride(S, p.sep) * 8);
     p.o_trail = take(J * sizeof(tno::TrailInfo));
@@ -677,11 +700,10 @@ hipError_t enqueue_front(Request *q, const tno_request *r, bool events)
     hipStream_t st = q->stream;
     void *A = q->arena;
     const Inputs in = inputs_of(q, r);
-    const int HW = p.H * p.W;
     hipError_t e;
     TRY(tno::launch_zero(st, at<int32_t>(A, p.o_err), 1));
-    TRY(tno::launch_ivar(st, HW, in.sigma, at<float>(A, p.o_iv32), at<double>(A, p.o_iv64),
-                         at<int32_t>(A, p.o_err)));
+    TRY(tno::launch_ivar(st, p.H, p.W, in.sigma, at<float>(A, p.o_iv32), at<double>(A, p.o_iv64), p.lHq,
+                         p.lWq, p.lPyt, p.lPxl, at<int32_t>(A, p.o_err)));
     TRY(tno::launch_prep_z(st, p.dtype, in.R, in.scales, at<float>(A, p.o_iv32), at<float4>(A, p.o_Z),
                            p.T, p.H, p.W, p.Hp, p.Wp4, p.Pt, p.Pl));
     if (events)
@@ -706,6 +728,9 @@ hipError_t enqueue_front(Request *q, const tno_request *r, bool events)
     la.ntx = p.lntx;
     la.nty = p.lnty;
     la.n_items = p.lntx * p.lnty * p.J;
+    la.Pyt = p.lPyt;
+    la.Pxl = p.lPxl;
+    la.Wq = p.lWq;
     TRY(tno::launch_lambda(st, la));
     if (events)
         TRY(hipEventRecord(q->ev[3], st));
