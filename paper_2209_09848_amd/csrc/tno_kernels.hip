@@ -961,12 +961,13 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
 template <int S, int NWAVE, int CPL, int RPL = 8, bool SEP = true>
 static void launch_search_t(hipStream_t st, const SearchArgs &a)
 {
-    // the shared-row form wherever it applies and its LDS (one window, two
-    // exchange buffers) keeps as many blocks per CU as two windows do
+    // the shared-row form wherever it applies, its LDS (one window, two
+    // exchange buffers) keeps as many blocks per CU as two windows do, and the
+    // block has at most 4 waves (with 8 its registers cost a wave per SIMD)
     constexpr int NWIN = (RPL * NWAVE + S - 1) * ((64 * CPL + S - 1 + 6) / 4);
     constexpr int LDS_X = NWIN * 16 + 2 * (NWAVE + 1) * (S - 1) * 64 * CPL * 4;
     constexpr int LDS_2 = 2 * NWIN * 16;
-    constexpr bool XCH = SEP && CPL % 2 == 0 && S > 1 && S - 1 <= RPL && NWAVE > 1 &&
+    constexpr bool XCH = SEP && CPL % 2 == 0 && S > 1 && S - 1 <= RPL && NWAVE > 1 && NWAVE <= 4 &&
                          LDS_PER_CU / LDS_X >= LDS_PER_CU / LDS_2;
     hipLaunchKernelGGL((k_search<S, NWAVE, CPL, RPL, SEP, XCH>), dim3(xcd_grid(a.n_items)),
                        dim3(64 * NWAVE), 0, st, a);
