@@ -32,9 +32,10 @@ constexpr int FRAME_CHUNK = 8;
 constexpr int LDS_PER_CU = 160 * 1024;   // gfx950 LDS bytes per compute unit
 
 // Dwords per offset/weight table entry, padded to 16 bytes: iy, ix and the
-// FP32 weights, gy[S], gx[S] for a separable (Gaussian) PRF or W[S][S]
-// (row-major) for a tabulated one.  The FP64 weights of the trail kernel
-// use the same order without the shifts: 2S or S*S doubles per entry.
+// FP32 weights, gy[S] gx[h] and gx[S] / gx[h] (the centre column tap folded
+// into the row taps) for a separable (Gaussian) PRF or W[S][S] (row-major)
+// for a tabulated one.  The FP64 weights of the trail kernel are gy[S],
+// gx[S] or W[S][S] without the shifts: 2S or S*S doubles per entry.
 __host__ __device__ constexpr int table_stride(int S, bool sep) { return (2 + (sep ? 2 * S : S * S) + 3) & ~3; }
 __host__ __device__ constexpr int table64_stride(int S, bool sep) { return sep ? 2 * S : S * S; }
 

@@ -320,9 +320,14 @@ __global__ void k_table(int J, int T, const double *__restrict__ times, double t
         double gy[TNO_MAX_STAMP], gx[TNO_MAX_STAMP];
         prf_profile(prf.kind, prf.sigma_px, S, fy, gy);
         prf_profile(prf.kind, prf.sigma_px, S, fx, gx);
+        // FP32 form for the search: the centre column tap (the largest of a
+        // unimodal unit-sum profile, so at least 1/S) is moved into the row
+        // weights, gy[a] gx[h] and gx[b] / gx[h], so that a horizontal pass
+        // starts from the centre value with no multiply; W = gy gx is unchanged
+        const int h = S / 2;
         for (int s = 0; s < S; ++s) {
-            t[2 + s] = __float_as_int((float)gy[s]);
-            t[2 + S + s] = __float_as_int((float)gx[s]);
+            t[2 + s] = __float_as_int((float)(gy[s] * gx[h]));
+            t[2 + S + s] = __float_as_int(s == h ? 1.0f : (float)(gx[s] / gx[h]));
             t64[s] = gy[s];
             t64[S + s] = gx[s];
         }
@@ -715,7 +720,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
                 if (k > k0)
                     halo(k - 1);
             }
-            float wt[NW];     // gy[S], gx[S] (separable) or W[S][S]
+            float wt[NW];     // gy[S] gx[h], gx[S] / gx[h] (separable) or W[S][S]
 #pragma unroll
             for (int s = 0; s < NW; ++s)
                 wt[s] = __int_as_float(e[2 + s]);
@@ -766,14 +771,17 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
                 }
             };
             // horizontal pass of one window row (separable stamp)
+            // (the table holds the column taps relative to the centre tap, whose
+            // weight is folded into the row taps)
             auto horiz = [&](const float (&v)[NV], float (&hs)[CPL]) {
                 if constexpr (SEP) {
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) {
-                        float sum = wt[S] * v[c];
+                        float sum = v[c + h];
 #pragma unroll
-                        for (int b = 1; b < S; ++b)
-                            sum = fmaf(wt[S + b], v[c + b], sum);
+                        for (int b = 0; b < S; ++b)
+                            if (b != h)
+                                sum = fmaf(wt[S + b], v[c + b], sum);
                         hs[c] = sum;
                     }
                 }
