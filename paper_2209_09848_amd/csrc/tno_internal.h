@@ -27,6 +27,9 @@ __host__ __device__ constexpr int search_ty(int v) { return SEARCH_VARIANTS[v].r
 // Normaliser tile: 64 columns (1 per lane) x 64 rows (16 per lane, 4 waves).
 constexpr int LAMBDA_TX = 64;
 constexpr int LAMBDA_TY = 64;
+// K values per normaliser chunk: every trail column run is zero-padded to a
+// whole number of chunks.
+constexpr int LAMBDA_CHUNK = 2;
 // Frames summed in FP32 before each FP64 accumulation of the numerator.
 constexpr int FRAME_CHUNK = 8;
 constexpr int LDS_PER_CU = 160 * 1024;   // gfx950 LDS bytes per compute unit

@@ -441,10 +441,11 @@ hipError_t launch_trail(hipStream_t st, int J, int T, int S, bool sep, const int
 // ------------------------------------------------------------------ k_lambda (FP64)
 
 // Lam_j(y, x) = sum over trail columns qx, rows qy of K_j(qy, qx) ivar(y+qy, x+qx).
-// A lane owns one image column x and 16 consecutive rows.  Each trail column's
-// run is zero-padded to whole chunks of 8 values; per chunk the 8 K values are
-// wave-uniform (scalar loads) and a sliding window of 23 ivar values down the
-// image column feeds 128 FP64 FMAs, each ivar load serving up to 16 outputs.
+// A lane owns one image column x and R = 16 consecutive rows.  Each trail
+// column's run is zero-padded to whole chunks of C = LAMBDA_CHUNK values; per
+// chunk the C K values are wave-uniform (scalar loads) and a sliding window of
+// R + C - 1 ivar values down the image column feeds R C FP64 FMAs, each ivar
+// load serving up to R outputs.
 // ivar is read from a copy with a zero border wide enough for every read of
 // the launch, so no load is clamped or masked: a wave's loads of one chunk are
 // buffer loads from a scalar base (the chunk's first row at the wave's first
@@ -452,7 +453,7 @@ hipError_t launch_trail(hipStream_t st, int J, int T, int S, bool sep, const int
 __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
 {
     constexpr int R = LAMBDA_TY / 4;   // outputs per lane (4 waves stacked)
-    constexpr int C = 8;               // K values per chunk
+    constexpr int C = LAMBDA_CHUNK;    // K values per chunk
     int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.n_items)
         return;
@@ -483,7 +484,11 @@ __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
             return __builtin_bit_cast(double, w);
         };
         const double *kv = a.kvals + ti.val_off + (int64_t)c * ti.cap;
-        double v[R + C - 1];
+        // the run's rows sit in a circular window, row i in slot i % NS, with
+        // the chunk loop unrolled over NS / C chunks so that every slot index
+        // is a constant and the window never moves
+        constexpr int NS = (R + C - 1 + C - 1) / C * C;
+        double v[NS];
         {
             const __amdgpu_buffer_rsrc_t rs =
                 __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, 0x7FFFFFFF, BUF_DWORD3);
@@ -491,24 +496,27 @@ __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
             for (int i = 0; i < R - 1; ++i)
                 v[i] = ld(rs, i);
         }
-        for (int q0 = 0; q0 < len; q0 += C) {
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void *)(base + (size_t)(q0 + R - 1) * a.Wq), (short)0, 0x7FFFFFFF, BUF_DWORD3);
+        for (int q0 = 0; q0 < len; q0 += NS) {
 #pragma unroll
-            for (int t = 0; t < C; ++t)
-                v[R - 1 + t] = ld(rs, t);
-            double kc[C];
-#pragma unroll
-            for (int t = 0; t < C; ++t)
-                kc[t] = kv[q0 + t];
-#pragma unroll
-            for (int r = 0; r < R; ++r)
+            for (int u = 0; u < NS / C; ++u) {
+                const int qq = q0 + u * C;
+                if (qq >= len)
+                    break;
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)(base + (size_t)(qq + R - 1) * a.Wq), (short)0, 0x7FFFFFFF, BUF_DWORD3);
 #pragma unroll
                 for (int t = 0; t < C; ++t)
-                    acc[r] = fma(kc[t], v[t + r], acc[r]);
+                    v[(u * C + R - 1 + t) % NS] = ld(rs, t);
+                double kc[C];
 #pragma unroll
-            for (int i = 0; i < R - 1; ++i)
-                v[i] = v[i + C];
+                for (int t = 0; t < C; ++t)
+                    kc[t] = kv[qq + t];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int t = 0; t < C; ++t)
+                        acc[r] = fma(kc[t], v[(u * C + t + r) % NS], acc[r]);
+            }
         }
     }
     if (x < a.W) {

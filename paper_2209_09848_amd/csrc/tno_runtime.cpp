@@ -280,7 +280,7 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
             if (c < (double)cap)
                 cap = (int)c;
         }
-        ti.cap = (int)align_up((size_t)std::max(cap, 1), 8);   // whole chunks of 8
+        ti.cap = (int)align_up((size_t)std::max(cap, 1), tno::LAMBDA_CHUNK);   // whole chunks
         ti.col_off = coff;
         ti.val_off = voff;
         coff += ti.ncols;
@@ -329,9 +329,9 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     {
         // The normaliser reads ivar at x + qx (x below lntx * TX, qx within a
         // trail box) and, down a column run [lo, lo + len) of rows inside
-        // [qy_lo, qy_hi], rows y0 + lo ... y0 + lo + round8(len) + R - 2 for a
-        // wave whose first row y0 is at most lnty * TY - R, i.e. at most
-        // lnty * TY + qy_hi + 6.  The border covers all of them.
+        // [qy_lo, qy_hi], rows y0 + lo ... y0 + lo + roundC(len) + R - 2 (C =
+        // LAMBDA_CHUNK) for a wave whose first row y0 is at most lnty * TY - R,
+        // i.e. at most lnty * TY + qy_hi + C - 2.  The border covers them all.
         int qxmin = 0, qxmax = 0, qymin = 0, qymax = 0;
         for (const auto &ti : p.trail) {
             if (ti.ncols <= 0)
@@ -344,7 +344,7 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
         p.lPxl = -qxmin;
         const int pxr = std::max(0, p.lntx * tno::LAMBDA_TX + qxmax - W);
         p.lPyt = -qymin;
-        const int pyb = std::max(0, p.lnty * tno::LAMBDA_TY + qymax + 7 - H);
+        const int pyb = std::max(0, p.lnty * tno::LAMBDA_TY + qymax + tno::LAMBDA_CHUNK - 1 - H);
         p.lWq = W + p.lPxl + pxr;
         p.lHq = H + p.lPyt + pyb;
     }
