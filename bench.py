@@ -67,6 +67,27 @@ def measured_traffic(updates_per_launch):
     return s.get("hbm_bytes_per_launch")
 
 
+def measured_copy_GBs():
+    """Bandwidth of a plain device copy (read + write bytes / time) recorded
+    beside the traffic counters, or None."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            return json.load(f).get("copy_probe", {}).get("copy_GBs")
+    except (OSError, ValueError):
+        return None
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def percentile(v, q):
     v = sorted(v)
     if not v:
@@ -110,14 +131,23 @@ def main():
     torch.cuda.set_device(dev)
 
     if args.copy_probe:
+        # a plain device copy of known size: scales the traffic counters and
+        # measures the copy bandwidth the chip reaches (read + write bytes / time)
         n = args.copy_probe * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        ev0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        ev1.record()
         torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
         print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
-                          "launches": 3}))
+                          "launches": 3 + reps, "copy_ms": ms, "copy_GBs": 2 * n * 4 / (ms * 1e-3) / 1e9}))
         return
 
     H, W, T = args.height, args.width, args.frames
@@ -160,6 +190,7 @@ def main():
     flop_per_update = 4 * 5                    # separable stamp: 2 x 5 FMAs per update
     achieved = flop_per_update * U / search_s / 1e12
     traffic = measured_traffic(U)
+    copy_GBs = measured_copy_GBs()
 
     cpu = None
     cpu_err = None
@@ -181,7 +212,24 @@ def main():
         cu = J * T * n * n
         cpu = {"value": cu / cdt, "unit": "updates/s", "cores": oracle.threads(), "kind": "oracle",
                "sample": "all %d trajectories x %d frames x %dx%d start pixels at the image centre "
-                         "(%.3g updates, %.1f s, FP64)" % (J, T, n, n, cu, cdt)}
+                         "(%.3g updates, %.1f s, FP64)" % (J, T, n, n, cu, cdt),
+               "cpu_model": cpu_model()}
+        # the same oracle on one core, over a smaller square of the same sample
+        n1 = max(8, n // 4)
+        all_threads = oracle.threads()
+        oracle.set_threads(1)
+        try:
+            c0 = time.perf_counter()
+            oracle.search(Rc, sc, times, t_ref, vel,
+                          region=(y0 - cy0, y0 - cy0 + n1, x0 - cx0, x0 - cx0 + n1))
+            cdt1 = time.perf_counter() - c0
+        finally:
+            oracle.set_threads(all_threads)
+        cu1 = J * T * n1 * n1
+        cpu["value_1core"] = cu1 / cdt1
+        cpu["sample_1core"] = ("all %d trajectories x %d frames x %dx%d start pixels at the image "
+                               "centre (%.3g updates, %.1f s, FP64, 1 thread)" % (J, T, n1, n1, cu1, cdt1))
+        log("oracle on 1 core: %.1f s -> %.3g updates/s" % (cdt1, cu1 / cdt1))
         g = o["snr"][:, y0:y0 + n, x0:x0 + n].cpu().numpy().astype(np.float64)
         cpu_err = float(np.max(np.abs(g - ora["snr"]) / np.maximum(1.0, np.abs(ora["snr"]))))
         log("oracle %.1f s -> %.3g updates/s; GPU vs oracle max SNR rel err %.2e" %
@@ -222,6 +270,12 @@ def main():
             "frac_nonpacked": achieved / PEAK_FP32_NONPACKED,
             "hbm_equiv_GBs": U * 4 / search_s / 1e9,
             "hbm_equiv_frac": U * 4 / search_s / 1e9 / PEAK_HBM_GBS,
+            # rocprof traffic over the kernel time, against the HBM peak and a
+            # measured plain copy
+            "traffic_GBs": traffic / search_s / 1e9 if traffic else None,
+            "traffic_frac_hbm": traffic / search_s / 1e9 / PEAK_HBM_GBS if traffic else None,
+            "copy_GBs": copy_GBs,
+            "traffic_frac_copy": traffic / search_s / 1e9 / copy_GBs if traffic and copy_GBs else None,
         },
         "cpu_baseline": cpu,
         "cpu_parity_max_rel_err": cpu_err,

@@ -292,3 +292,14 @@ int oracle_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the following calls (timing on one core and on all of them). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}

@@ -70,6 +70,8 @@ def _load():
                  ctypes.c_int, ctypes.c_int, P(i32), P(i32), P(i32), P(d), P(d)]
             lib.oracle_hypotheses.restype = ctypes.c_int
             lib.oracle_threads.restype = ctypes.c_int
+            lib.oracle_set_threads.argtypes = [ctypes.c_int]
+            lib.oracle_set_threads.restype = None
             _lib = lib
     return _lib
 
@@ -81,6 +83,11 @@ def _ptr(a, ctype):
 def threads() -> int:
     """OpenMP threads the oracle runs with."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads for the following oracle calls."""
+    _load().oracle_set_threads(int(n))
 
 
 def resolve_t_ref(times, t_ref):
