@@ -76,6 +76,8 @@ struct SearchArgs {
     int ntx, nty, n_items;
     int tblock;              // trajectories per block of the work order
     int nframes;             // frames to accumulate (T, or fewer for a tuning probe)
+    int kstride;             // frame k of the launch is frame k * kstride of the stack (1; a
+                             // tuning probe spreads its frames over the whole sequence)
 };
 
 struct LambdaArgs {

@@ -616,6 +616,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
 
     // Fetch the window of frame k into registers; returns its sub-float4 offset.
     auto fetch = [&](int k, float4 (&pre)[NLD]) -> int {
+        k *= a.kstride;
         const cint32_t *e = tabj + (size_t)k * TS;
         const int oy = ty0 + e[0] - h + a.Pt;
         const int ox = tx0 + e[1] - h + a.Pl;
@@ -723,7 +724,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
             // branch around the prefetch, so its store stays behind the arithmetic
             const int d_next = fetch(min(k + 1, a.nframes - 1), pre);
 
-            const cint32_t *e = tabj + (size_t)k * TS;
+            const cint32_t *e = tabj + (size_t)k * a.kstride * TS;
             if constexpr (XCH) {
                 if (k > k0)
                     halo(k - 1);
