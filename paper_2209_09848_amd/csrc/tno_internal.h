@@ -44,13 +44,17 @@ __host__ __device__ constexpr int table64_stride(int S, bool sep) { return sep ?
 
 // Per-trajectory layout of the collapsed trail kernel K_j (column runs).
 struct TrailInfo {
-    int32_t qx0;       // first column offset of the trail box
-    int32_t ncols;     // columns in the box (clipped to |qx| < W)
-    int32_t qy_lo;     // smallest row offset kept (clipped to > -H)
-    int32_t qy_hi;     // largest row offset kept (clipped to < H)
-    int32_t cap;       // stride of one column run: a multiple of 8, zero-padded
-    int32_t pad;
-    int64_t col_off;   // index of this trajectory's first column record
+    // tr = 0: the box's columns are the major axis and each column's run goes
+    // down the rows.  tr = 1 (boxes wider than tall): stored transposed, the
+    // box's rows are the major axis (qx0, ncols = first row offset, rows) and
+    // each row's run goes along the columns (qy_lo, qy_hi = column offsets).
+    int32_t qx0;       // first major offset of the trail box
+    int32_t ncols;     // major lines in the box (clipped to |q| below the image side)
+    int32_t qy_lo;     // smallest minor offset kept (clipped likewise)
+    int32_t qy_hi;     // largest minor offset kept
+    int32_t cap;       // stride of one run: a multiple of LAMBDA_CHUNK, zero-padded
+    int32_t tr;        // 1: stored transposed
+    int64_t col_off;   // index of this trajectory's first run record
     int64_t val_off;   // index of this trajectory's first K value
 };
 
@@ -80,20 +84,29 @@ struct SearchArgs {
                              // tuning probe spreads its frames over the whole sequence)
 };
 
+// One launch of the normaliser covers the trajectories of one storage
+// orientation; a transposed launch works in the transposed image (rows <->
+// columns) and writes Lam back in the image's own layout.
 struct LambdaArgs {
     const TrailInfo *info;
-    const int2 *colmeta;     // per column: (row offset of run start, run length)
+    const int2 *colmeta;     // per major line: (minor offset of run start, run length)
     const double *kvals;
-    const double *ivar64;    // [Hq][Wq]: ivar at (Pyt + y, Pxl + x), zero around it
-    double *lam;             // [J][H][W]
-    int H, W, J, ntx, nty, n_items;
+    const double *ivar64;    // [Hq][Wq] in the launch's frame: ivar at (Pyt + y, Pxl + x), zero around it
+    double *lam;             // [J][H0][W0]
+    const int32_t *jlist;    // [nj] trajectories of this launch
+    int H, W;                // image in the launch's frame (W0, H0 when transposed)
+    int H0, W0;              // image
+    int nj, ntx, nty, n_items;
     int Pyt, Pxl, Wq;
+    int tr;                  // 1: transposed launch
 };
 
 // ---- launch wrappers (all on `st`; return hipError_t of the launch)
 hipError_t launch_zero(hipStream_t st, int32_t *p, int n);
+// ivar32 [H][W] (when not NULL) and the zero-bordered FP64 map [Hq][Wq] of
+// the image (tr = 0) or of its transpose (tr = 1).
 hipError_t launch_ivar(hipStream_t st, int H, int W, const float *sigma, float *ivar32, double *ivar64,
-                       int Hq, int Wq, int Pyt, int Pxl, int32_t *err);
+                       int Hq, int Wq, int Pyt, int Pxl, int tr, int32_t *err);
 hipError_t launch_prep_z(hipStream_t st, int dtype, const void *R, const float *scales,
                          const float *ivar32, float4 *Z4, int T, int H, int W, int Hp, int Wp4,
                          int Pt, int Pl);

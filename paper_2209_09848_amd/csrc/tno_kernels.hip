@@ -79,35 +79,38 @@ hipError_t launch_zero(hipStream_t st, int32_t *p, int n)
 // ------------------------------------------------------------------ k_ivar
 
 __global__ void k_ivar(int W, const float *__restrict__ sigma, float *__restrict__ ivar32,
-                       double *__restrict__ ivar64, int64_t HWq, int Wq, int H, int Pyt, int Pxl,
+                       double *__restrict__ ivar64, int64_t HWq, int Wq, int H, int Pyt, int Pxl, int tr,
                        int32_t *__restrict__ err)
 {
-    // one thread per element of the zero-bordered FP64 map
+    // one thread per element of the zero-bordered FP64 map; with tr its rows
+    // are the image's columns
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < HWq; q += (int64_t)gridDim.x * blockDim.x) {
         const int yq = (int)(q / Wq), xq = (int)(q - (int64_t)yq * Wq);
-        const int y = yq - Pyt, x = xq - Pxl;
+        const int y = tr ? xq - Pxl : yq - Pyt, x = tr ? yq - Pyt : xq - Pxl;
         double iv = 0.0;
         if ((unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W) {
             const size_t p = (size_t)y * W + x;
             const double s = (double)sigma[p];
             iv = (__builtin_isfinite(s) && s > 0.0) ? 1.0 / (s * s) : 0.0;
-            const float iv32 = (float)iv;
-            if (!__builtin_isfinite(iv32))
-                atomicOr(err, 2);     // 1/sigma^2 beyond single precision: rejected
-            ivar32[p] = iv32;
+            if (ivar32) {
+                const float iv32 = (float)iv;
+                if (!__builtin_isfinite(iv32))
+                    atomicOr(err, 2);     // 1/sigma^2 beyond single precision: rejected
+                ivar32[p] = iv32;
+            }
         }
         ivar64[q] = iv;
     }
 }
 
 hipError_t launch_ivar(hipStream_t st, int H, int W, const float *sigma, float *ivar32, double *ivar64,
-                       int Hq, int Wq, int Pyt, int Pxl, int32_t *err)
+                       int Hq, int Wq, int Pyt, int Pxl, int tr, int32_t *err)
 {
     const int64_t n = (int64_t)Hq * Wq;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_ivar, dim3((unsigned)blocks), dim3(256), 0, st, W, sigma, ivar32, ivar64, n, Wq, H,
-                       Pyt, Pxl, err);
+                       Pyt, Pxl, tr, err);
     return hipGetLastError();
 }
 
@@ -357,11 +360,12 @@ hipError_t launch_table(hipStream_t st, int J, int T, const double *times, doubl
 
 // ------------------------------------------------------------------ k_trail (FP64)
 
-// One block per trajectory, one thread per column offset qx of the trail box.
+// One block per trajectory, one thread per major offset of the trail box
+// (a column offset qx, or a row offset qy for a box stored transposed).
 // K_j(qy, qx) = sum_k W_jk(qy - iy_k, qx - ix_k)^2 over the frames whose
-// stamp covers (qy, qx); each column is one contiguous run of rows, summed
-// frame by frame in frame order (deterministic).  W is gy*gx for a separable
-// PRF, the tabulated weight otherwise.
+// stamp covers (qy, qx); each major line is one contiguous run along the
+// minor axis, summed frame by frame in frame order (deterministic).  W is
+// gy*gx for a separable PRF, the tabulated weight otherwise.
 __global__ void k_trail(int T, int S, int sep, const int32_t *__restrict__ tab32,
                         const double *__restrict__ tab64, const TrailInfo *__restrict__ info,
                         int2 *__restrict__ colmeta, double *__restrict__ kvals,
@@ -374,16 +378,18 @@ __global__ void k_trail(int T, int S, int sep, const int32_t *__restrict__ tab32
     const int T64 = table64_stride(S, sep);
     const int32_t *tj = tab32 + (size_t)j * T * TS;
     const double *t64 = tab64 + (size_t)j * T * T64;
+    // major axis: x (tr = 0) or y (tr = 1); table entries hold (iy, ix)
+    const int mj = ti.tr ? 0 : 1, mn = 1 - mj;
     for (int c = threadIdx.x; c < ti.ncols; c += blockDim.x) {
-        const int qx = ti.qx0 + c;
+        const int qm = ti.qx0 + c;
         int lo = INT_MAX, hi = INT_MIN;
         for (int k = 0; k < T; ++k) {
-            int ix = tj[(size_t)k * TS + 1];
-            int dxo = qx - ix;
-            if (dxo >= -h && dxo <= h) {
-                int iy = tj[(size_t)k * TS + 0];
-                lo = min(lo, iy - h);
-                hi = max(hi, iy + h);
+            int im = tj[(size_t)k * TS + mj];
+            int dmo = qm - im;
+            if (dmo >= -h && dmo <= h) {
+                int in = tj[(size_t)k * TS + mn];
+                lo = min(lo, in - h);
+                hi = max(hi, in + h);
             }
         }
         lo = max(lo, ti.qy_lo);
@@ -400,28 +406,30 @@ __global__ void k_trail(int T, int S, int sep, const int32_t *__restrict__ tab32
         if (len == 0)
             continue;
         for (int k = 0; k < T; ++k) {
-            int ix = tj[(size_t)k * TS + 1];
-            int dxo = qx - ix;
-            if (dxo < -h || dxo > h)
+            int im = tj[(size_t)k * TS + mj];
+            int dmo = qm - im;
+            if (dmo < -h || dmo > h)
                 continue;
-            int iy = tj[(size_t)k * TS + 0];
+            int in = tj[(size_t)k * TS + mn];
             const double *wk = t64 + (size_t)k * T64;
+            // tap (a along y, b along x) of the stamp: the major tap is fixed
+            // (dmo + h), the minor one runs
             if (sep) {
-                double wx = wk[S + dxo + h];
-                double wx2 = wx * wx;
-                for (int a = 0; a < S; ++a) {
-                    int r = iy - h + a - lo;
+                double wm = ti.tr ? wk[dmo + h] : wk[S + dmo + h];
+                double wm2 = wm * wm;
+                for (int t = 0; t < S; ++t) {
+                    int r = in - h + t - lo;
                     if (r < 0 || r >= len)
                         continue;
-                    double wy = wk[a];
-                    kv[r] += wx2 * (wy * wy);
+                    double wn = ti.tr ? wk[S + t] : wk[t];
+                    kv[r] += wm2 * (wn * wn);
                 }
             } else {
-                for (int a = 0; a < S; ++a) {
-                    int r = iy - h + a - lo;
+                for (int t = 0; t < S; ++t) {
+                    int r = in - h + t - lo;
                     if (r < 0 || r >= len)
                         continue;
-                    double w = wk[a * S + dxo + h];
+                    double w = ti.tr ? wk[(dmo + h) * S + t] : wk[t * S + dmo + h];
                     kv[r] += w * w;
                 }
             }
@@ -441,6 +449,8 @@ hipError_t launch_trail(hipStream_t st, int J, int T, int S, bool sep, const int
 // ------------------------------------------------------------------ k_lambda (FP64)
 
 // Lam_j(y, x) = sum over trail columns qx, rows qy of K_j(qy, qx) ivar(y+qy, x+qx).
+// (Boxes wider than tall run in the transposed image: the same computation
+// with rows and columns exchanged, the result written back untransposed.)
 // A lane owns one image column x and R = 16 consecutive rows.  Each trail
 // column's run is zero-padded to whole chunks of C = LAMBDA_CHUNK values; per
 // chunk the C K values are wave-uniform (scalar loads) and a sliding window of
@@ -457,8 +467,8 @@ __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
     int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= a.n_items)
         return;
-    const int j = item % a.J;
-    const int tile = item / a.J;
+    const int j = a.jlist[item % a.nj];
+    const int tile = item / a.nj;
     const int tyi = tile / a.ntx, txi = tile - tyi * a.ntx;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -523,8 +533,11 @@ __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             int y = y0 + r;
-            if (y < a.H)
-                a.lam[((size_t)j * a.H + y) * a.W + x] = acc[r];
+            if (y < a.H) {
+                // (y, x) of the launch's frame; transposed: image row x, column y
+                const size_t o = a.tr ? ((size_t)j * a.H0 + x) * a.W0 + y : ((size_t)j * a.H0 + y) * a.W0 + x;
+                a.lam[o] = acc[r];
+            }
         }
     }
 }

@@ -85,8 +85,16 @@ struct Plan {
     int variant = 0, tblock = 1;      // search tile shape and trajectory block of the work order
     int ntiles_max = 0;               // tiles of the smallest shape (sizes the tile-key buffer)
     std::vector<int32_t> perm;        // velocity-sorted search order
-    int lntx = 0, lnty = 0;
-    int lPyt = 0, lPxl = 0, lHq = 0, lWq = 0;   // zero border of the FP64 ivar map
+    // normaliser launches: [0] trails stored by columns, [1] by rows (run in
+    // the transposed image); each with its zero-bordered FP64 ivar map
+    struct LamLaunch {
+        int nj = 0, joff = 0;          // trajectories, first index in `jlist`
+        int Hf = 0, Wf = 0;            // image in the launch's frame
+        int ntx = 0, nty = 0;
+        int Pyt = 0, Pxl = 0, Hq = 0, Wq = 0;
+        size_t o_map = 0;
+    } lam[2];
+    std::vector<int32_t> jlist;       // trajectories of launch 0, then of launch 1
     int64_t N = 0, n_chunks = 0;
     bool own_snr = true, own_flux = true;
     int box = 0, kdet = 0;            // significance window side; detections wanted
@@ -99,7 +107,7 @@ struct Plan {
            o_err = 0, o_lam = 0, o_snr = 0, o_flux = 0, o_tkeys = 0, o_tstate = 0, o_chunks = 0,
            o_cand = 0, o_tmax = 0, o_topk = 0, o_best = 0, o_bestj = 0, o_perm = 0, o_r1 = 0,
            o_r2 = 0, o_b1 = 0, o_b2 = 0, o_sig = 0, o_det = 0, o_counts = 0, o_prf = 0, o_jit = 0,
-           bytes = 0;
+           o_jl = 0, bytes = 0;
 };
 
 bool finite(double v) { return std::isfinite(v); }
@@ -266,19 +274,24 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
         gymin = std::min(gymin, ylo);
         gymax = std::max(gymax, yhi);
         tno::TrailInfo ti{};
-        int qx0 = std::max(xlo - h, -(W - 1)), qx1 = std::min(xhi + h, W - 1);
-        ti.qx0 = qx0;
-        ti.ncols = std::max(0, qx1 - qx0 + 1);
-        ti.qy_lo = std::max(ylo - h, -(H - 1));
-        ti.qy_hi = std::min(yhi + h, H - 1);
-        int nrows = std::max(0, ti.qy_hi - ti.qy_lo + 1);
-        int cap = nrows;
-        if (vx != 0.0) {
-            // frames whose stamp covers one column have |v_x dt + theta_x - qx| <= h + 1/2:
-            // a time span of (S + jitter range in x) / |vx|, over which the row
-            // anchor moves by |vy| times that plus the jitter range in y
-            double c = std::ceil((double)S + ((double)S + (jxmax - jxmin)) * std::fabs(vy) / std::fabs(vx) +
-                                 (jymax - jymin)) + 3.0;
+        const int qx0 = std::max(xlo - h, -(W - 1)), qx1 = std::min(xhi + h, W - 1);
+        const int qy0 = std::max(ylo - h, -(H - 1)), qy1 = std::min(yhi + h, H - 1);
+        const int ncols = std::max(0, qx1 - qx0 + 1), nrows = std::max(0, qy1 - qy0 + 1);
+        // a box wider than tall is stored by rows: its runs along x are the
+        // long ones, and the normaliser reloads ivar once per run
+        ti.tr = ncols > nrows ? 1 : 0;
+        // frames whose stamp covers one major line have |v_m dt + theta_m - q| <= h + 1/2:
+        // a time span of (S + jitter range along it) / |v_m|, over which the
+        // minor anchor moves by |v_n| times that plus its jitter range
+        const double vm = ti.tr ? vy : vx, vn = ti.tr ? vx : vy;
+        const double jm = ti.tr ? jymax - jymin : jxmax - jxmin, jn = ti.tr ? jxmax - jxmin : jymax - jymin;
+        ti.qx0 = ti.tr ? qy0 : qx0;
+        ti.ncols = ti.tr ? nrows : ncols;
+        ti.qy_lo = ti.tr ? qx0 : qy0;
+        ti.qy_hi = ti.tr ? qx1 : qy1;
+        int cap = ti.tr ? ncols : nrows;
+        if (vm != 0.0) {
+            double c = std::ceil((double)S + ((double)S + jm) * std::fabs(vn) / std::fabs(vm) + jn) + 3.0;
             if (c < (double)cap)
                 cap = (int)c;
         }
@@ -328,18 +341,29 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
         std::iota(p.perm.begin(), p.perm.end(), 0);
         std::stable_sort(p.perm.begin(), p.perm.end(), [&](int32_t x, int32_t y) { return code[x] < code[y]; });
     }
-    p.lntx = (W + tno::LAMBDA_TX - 1) / tno::LAMBDA_TX;
-    p.lnty = (H + tno::LAMBDA_TY - 1) / tno::LAMBDA_TY;
-    if ((double)p.lntx * p.lnty * p.J > 2.0e9)
-        return fail(TNO_E_INVAL, "too many normaliser work items");
-    {
-        // The normaliser reads ivar at x + qx (x below lntx * TX, qx within a
-        // trail box) and, down a column run [lo, lo + len) of rows inside
-        // [qy_lo, qy_hi], rows y0 + lo ... y0 + lo + roundC(len) + R - 2 (C =
-        // LAMBDA_CHUNK) for a wave whose first row y0 is at most lnty * TY - R,
-        // i.e. at most lnty * TY + qy_hi + C - 2.  The border covers them all.
+    p.jlist.clear();
+    for (int o = 0; o < 2; ++o) {
+        auto &L = p.lam[o];
+        L.joff = (int)p.jlist.size();
+        for (int j = 0; j < p.J; ++j)
+            if (p.trail[j].tr == o)
+                p.jlist.push_back(j);
+        L.nj = (int)p.jlist.size() - L.joff;
+        L.Hf = o ? W : H;
+        L.Wf = o ? H : W;
+        L.ntx = (L.Wf + tno::LAMBDA_TX - 1) / tno::LAMBDA_TX;
+        L.nty = (L.Hf + tno::LAMBDA_TY - 1) / tno::LAMBDA_TY;
+        if ((double)L.ntx * L.nty * L.nj > 2.0e9)
+            return fail(TNO_E_INVAL, "too many normaliser work items");
+        // In the launch's frame the normaliser reads ivar at x + q (x below
+        // ntx * TX, q a major offset of a box) and, along a run [lo, lo +
+        // len) of minor offsets inside [qy_lo, qy_hi], rows y0 + lo ... y0 +
+        // lo + roundC(len) + R - 2 (C = LAMBDA_CHUNK) for a wave whose first
+        // row y0 is at most nty * TY - R, i.e. at most nty * TY + qy_hi + C -
+        // 2.  The border covers them all.
         int qxmin = 0, qxmax = 0, qymin = 0, qymax = 0;
-        for (const auto &ti : p.trail) {
+        for (int i = 0; i < L.nj; ++i) {
+            const auto &ti = p.trail[p.jlist[L.joff + i]];
             if (ti.ncols <= 0)
                 continue;
             qxmin = std::min(qxmin, ti.qx0);
@@ -347,12 +371,12 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
             qymin = std::min(qymin, ti.qy_lo);
             qymax = std::max(qymax, ti.qy_hi);
         }
-        p.lPxl = -qxmin;
-        const int pxr = std::max(0, p.lntx * tno::LAMBDA_TX + qxmax - W);
-        p.lPyt = -qymin;
-        const int pyb = std::max(0, p.lnty * tno::LAMBDA_TY + qymax + tno::LAMBDA_CHUNK - 1 - H);
-        p.lWq = W + p.lPxl + pxr;
-        p.lHq = H + p.lPyt + pyb;
+        L.Pxl = -qxmin;
+        const int pxr = std::max(0, L.ntx * tno::LAMBDA_TX + qxmax - L.Wf);
+        L.Pyt = -qymin;
+        const int pyb = std::max(0, L.nty * tno::LAMBDA_TY + qymax + tno::LAMBDA_CHUNK - 1 - L.Hf);
+        L.Wq = L.Wf + L.Pxl + pxr;
+        L.Hq = L.Hf + L.Pyt + pyb;
     }
     p.N = (int64_t)p.J * H * W;
     p.k = (int)std::min<int64_t>(r->top_k, p.N);
@@ -391,7 +415,9 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     }
     p.o_Z = take(T * (size_t)p.Hp * p.Wp4 * 16);
     p.o_iv32 = take(HW * 4);
-    p.o_iv64 = take((size_t)p.lHq * p.lWq * 8);
+    for (auto &L : p.lam)
+        L.o_map = L.nj > 0 || &L == &p.lam[0] ? take((size_t)L.Hq * L.Wq * 8) : 0;
+    p.o_jl = take(J * 4);
     p.o_tab32 = take(J * T * tno::table_stride(S, p.sep) * 4);
     p.o_tab64 = take(J * T * tno::table64_stride(S, p.sep) * 8);
     p.o_trail = take(J * sizeof(tno::TrailInfo));
@@ -696,6 +722,8 @@ hipError_t enqueue_pre(Request *q)
                        hipMemcpyHostToDevice, st));
     TRY(hipMemcpyAsync(at<void>(A, p.o_perm), p.perm.data(), p.perm.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice, st));
+    TRY(hipMemcpyAsync(at<void>(A, p.o_jl), p.jlist.data(), p.jlist.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, st));
     return hipSuccess;
 }
 
@@ -709,8 +737,12 @@ hipError_t enqueue_front(Request *q, const tno_request *r, bool events)
     const Inputs in = inputs_of(q, r);
     hipError_t e;
     TRY(tno::launch_zero(st, at<int32_t>(A, p.o_err), 1));
-    TRY(tno::launch_ivar(st, p.H, p.W, in.sigma, at<float>(A, p.o_iv32), at<double>(A, p.o_iv64), p.lHq,
-                         p.lWq, p.lPyt, p.lPxl, at<int32_t>(A, p.o_err)));
+    for (int o = 0; o < 2; ++o) {
+        const auto &L = p.lam[o];
+        if (o == 0 || L.nj > 0)
+            TRY(tno::launch_ivar(st, p.H, p.W, in.sigma, o == 0 ? at<float>(A, p.o_iv32) : nullptr,
+                                 at<double>(A, L.o_map), L.Hq, L.Wq, L.Pyt, L.Pxl, o, at<int32_t>(A, p.o_err)));
+    }
     TRY(tno::launch_prep_z(st, p.dtype, in.R, in.scales, at<float>(A, p.o_iv32), at<float4>(A, p.o_Z),
                            p.T, p.H, p.W, p.Hp, p.Wp4, p.Pt, p.Pl));
     if (events)
@@ -723,22 +755,31 @@ hipError_t enqueue_front(Request *q, const tno_request *r, bool events)
                           at<double>(A, p.o_kvals), at<int32_t>(A, p.o_err)));
     if (events)
         TRY(hipEventRecord(q->ev[2], st));
-    tno::LambdaArgs la;
-    la.info = at<tno::TrailInfo>(A, p.o_trail);
-    la.colmeta = at<int2>(A, p.o_colmeta);
-    la.kvals = at<double>(A, p.o_kvals);
-    la.ivar64 = at<double>(A, p.o_iv64);
-    la.lam = at<double>(A, p.o_lam);
-    la.H = p.H;
-    la.W = p.W;
-    la.J = p.J;
-    la.ntx = p.lntx;
-    la.nty = p.lnty;
-    la.n_items = p.lntx * p.lnty * p.J;
-    la.Pyt = p.lPyt;
-    la.Pxl = p.lPxl;
-    la.Wq = p.lWq;
-    TRY(tno::launch_lambda(st, la));
+    for (int o = 0; o < 2; ++o) {
+        const auto &L = p.lam[o];
+        if (L.nj == 0)
+            continue;
+        tno::LambdaArgs la;
+        la.info = at<tno::TrailInfo>(A, p.o_trail);
+        la.colmeta = at<int2>(A, p.o_colmeta);
+        la.kvals = at<double>(A, p.o_kvals);
+        la.ivar64 = at<double>(A, L.o_map);
+        la.lam = at<double>(A, p.o_lam);
+        la.jlist = at<int32_t>(A, p.o_jl) + L.joff;
+        la.H = L.Hf;
+        la.W = L.Wf;
+        la.H0 = p.H;
+        la.W0 = p.W;
+        la.nj = L.nj;
+        la.ntx = L.ntx;
+        la.nty = L.nty;
+        la.n_items = L.ntx * L.nty * L.nj;
+        la.Pyt = L.Pyt;
+        la.Pxl = L.Pxl;
+        la.Wq = L.Wq;
+        la.tr = o;
+        TRY(tno::launch_lambda(st, la));
+    }
     if (events)
         TRY(hipEventRecord(q->ev[3], st));
     return hipSuccess;
@@ -882,8 +923,8 @@ std::string graph_key(const Request *q)
     char buf[256];
     snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %u", p.H, p.W, p.T,
              p.J, p.S, (int)p.sep, p.kind, p.variant, p.tblock, p.dtype, p.k, p.box, p.kdet,
-             (int)p.own_snr, (int)p.own_flux, (int)p.dev, (int)p.jitter, p.Hp, p.Wp4, p.lntx, p.lnty,
-             copies);
+             (int)p.own_snr, (int)p.own_flux, (int)p.dev, (int)p.jitter, p.Hp, p.Wp4, p.lam[0].nj > 0,
+             p.lam[1].nj > 0, copies);
     return buf;
 }
 
