@@ -24,9 +24,9 @@ constexpr int SEARCH_MAX_TX = 256;
 constexpr int SEARCH_MAX_TY = 64;
 __host__ __device__ constexpr int search_tx(int v) { return 64 * SEARCH_VARIANTS[v].cpl; }
 __host__ __device__ constexpr int search_ty(int v) { return SEARCH_VARIANTS[v].rpl * SEARCH_VARIANTS[v].nwave; }
-// Normaliser tile: 64 columns (1 per lane) x 64 rows (16 per lane, 4 waves).
+// Normaliser tile: 64 columns (1 per lane) x 128 rows (32 per lane, 4 waves).
 constexpr int LAMBDA_TX = 64;
-constexpr int LAMBDA_TY = 64;
+constexpr int LAMBDA_TY = 128;
 // K values per normaliser chunk: every trail column run is zero-padded to a
 // whole number of chunks.
 constexpr int LAMBDA_CHUNK = 2;

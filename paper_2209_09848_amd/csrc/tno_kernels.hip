@@ -451,7 +451,7 @@ hipError_t launch_trail(hipStream_t st, int J, int T, int S, bool sep, const int
 // Lam_j(y, x) = sum over trail columns qx, rows qy of K_j(qy, qx) ivar(y+qy, x+qx).
 // (Boxes wider than tall run in the transposed image: the same computation
 // with rows and columns exchanged, the result written back untransposed.)
-// A lane owns one image column x and R = 16 consecutive rows.  Each trail
+// A lane owns one image column x and R = 32 consecutive rows.  Each trail
 // column's run is zero-padded to whole chunks of C = LAMBDA_CHUNK values; per
 // chunk the C K values are wave-uniform (scalar loads) and a sliding window of
 // R + C - 1 ivar values down the image column feeds R C FP64 FMAs, each ivar
