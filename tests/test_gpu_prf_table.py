@@ -197,3 +197,19 @@ def test_ffi_full_size_tabulated_with_jitter_sampled_parity():
                             prf_q=9, jitter=jitter,
                             region=(y0 - cy0, y1 - cy0, x0 - cx0, x1 - cx0))
         parity.check_maps(snr[:, y0:y1, x0:x1].cpu().numpy(), flux[:, y0:y1, x0:x1].cpu().numpy(), ora)
+
+
+@pytest.mark.parametrize("kind,stamp", [(0, 5), (1, 7), ("table", 5), ("table", 7)])
+def test_both_trail_orientations(kind, stamp):
+    """A bank with horizontal, vertical, diagonal and standing trajectories:
+    the normaliser stores a trail box by rows when it is wider than tall and
+    by columns otherwise, and runs the two groups in separate launches; every
+    map must match the oracle whichever way a trajectory was stored."""
+    T, H, W = 40, 60, 150
+    g, R, sigma, times, _ = _problem(300 + stamp, T, H, W, 1)
+    vel = np.array([[40.0, 0.0], [-35.0, 3.0], [0.0, 30.0], [2.5, -28.0], [20.0, 20.0],
+                    [-21.0, 19.0], [0.0, 0.0], [60.0, -1.0]])
+    table, q = (synth.TabulatedPSF().table(stamp, 5), 5) if kind == "table" else (None, 0)
+    jitter = synth.jitter_series(g, T, amp=0.15)
+    _check(R, sigma, times, vel, float(times[0]), stamp, oracle.PRF_TABLE if kind == "table" else kind,
+           table=table, q=q, jitter=jitter)
