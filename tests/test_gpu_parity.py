@@ -83,6 +83,9 @@ def _rand_problem(seed, T, H, W, J, vmax=20.0, mask=True, gap=True):
     (6, 33, 129, 2, 1, 0),       # single-tap stamp
     (6, 40, 70, 2, 3, 0),
     (5, 45, 50, 2, 7, 1),
+    (5, 41, 150, 3, 9, 0),       # shared rows would cost a block per CU: per-wave halo rows
+    (4, 39, 140, 2, 11, 1),      # S - 1 above the rows per lane: per-wave halo rows
+    (4, 47, 131, 2, 13, 0),
     (4, 50, 140, 2, 15, 0),      # widest stamp
     (300, 34, 40, 3, 5, 0),      # many frame chunks
     (1, 1, 1, 1, 5, 0),          # a single pixel, a single frame
