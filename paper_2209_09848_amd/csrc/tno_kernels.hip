@@ -731,7 +731,10 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
     __syncthreads();
     for (int k0 = 0; k0 < a.nframes; k0 += FRAME_CHUNK) {
         const int k1 = min(k0 + FRAME_CHUNK, a.nframes);
-        for (int k = k0; k < k1; ++k) {
+        // one frame; the first frame of a chunk has no pending halo rows (the
+        // previous chunk added them), so it is peeled off and the loop body
+        // adds them unconditionally
+        auto frame = [&](int k, bool do_halo) __attribute__((always_inline)) {
             const int buf = XCH ? 0 : (k & 1);
             // the last iteration re-fetches frame T-1 into the idle buffer: no
             // branch around the prefetch, so its store stays behind the arithmetic
@@ -739,7 +742,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
 
             const cint32_t *e = tabj + (size_t)k * a.kstride * TS;
             if constexpr (XCH) {
-                if (k > k0)
+                if (do_halo)
                     halo(k - 1);
             }
             float wt[NW];     // gy[S] gx[h], gx[S] / gx[h] (separable) or W[S][S]
@@ -881,7 +884,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
                     wyp[aa] = wt[aa];
                 __syncthreads();
                 d_cur = d_next;
-                continue;
+                return;
             }
             // window rows are read one row ahead of their use (the loop is
             // unrolled, so the two buffers are register renames)
@@ -928,7 +931,10 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
             store(buf ^ 1, pre);
             __syncthreads();
             d_cur = d_next;
-        }
+        };
+        frame(k0, false);
+        for (int k = k0 + 1; k < k1; ++k)
+            frame(k, true);
         if constexpr (XCH)
             halo(k1 - 1);
         // frame chunk done: into the FP64 totals
