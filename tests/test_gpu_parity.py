@@ -256,8 +256,9 @@ def _crop_oracle(R_dev, sigma, times, t_ref, vel, y0, y1, x0, x1, margin):
 def test_ffi_full_size_sampled_parity():
     """2048x2048 px x 1000 frames, 100 trajectories, 30 sources: the launch
     configuration the benchmark times.  Oracle on sampled start pixels (all
-    trajectories) in a corner, an edge and the centre, and at injected
-    sources; reductions checked against torch ops on the GPU's own maps."""
+    trajectories) in a corner, an edge and the centre, at every fifth top-k
+    candidate and at injected sources; reductions checked against torch ops
+    on the GPU's own maps."""
     H = W = 2048
     T = 1000
     print("generating FFI-size problem", flush=True)
@@ -298,6 +299,12 @@ def test_ffi_full_size_sampled_parity():
         ora = _crop_oracle(R, sigma, times, t_ref, vel, y0, y1, x0, x1, margin)
         sub = {"snr": snr[:, y0:y1, x0:x1].cpu().numpy(), "flux": flux[:, y0:y1, x0:x1].cpu().numpy()}
         parity.check_maps(sub["snr"], sub["flux"], ora)
+    # every fifth top-k candidate: its SNR and flux against the oracle at its
+    # own (trajectory, start pixel)
+    for c in cands[::5]:
+        _, _, j, y, x = c
+        ora = _crop_oracle(R, sigma, times, t_ref, vel[j:j + 1], y, y + 1, x, x + 1, margin)
+        parity.check_maps(np.array([[[c[0]]]], np.float32), np.array([[[c[1]]]], np.float32), ora)
     # injected sources: truth trajectory around the rounded start
     for s in src[:6]:
         j = s.traj
