@@ -171,7 +171,7 @@ def test_injected_tabulated_source_recovered_at_truth():
 def test_ffi_full_size_tabulated_with_jitter_sampled_parity():
     """2048x2048 px x 1000 frames, 100 trajectories, with the tabulated PSF
     (q = 9) and a +-0.15 px jitter series: oracle on sampled start pixels in
-    a corner, an edge and the centre."""
+    a corner, an edge and the centre, and at every fifth top-k candidate."""
     H = W = 2048
     T = 1000
     print("generating FFI-size problem", flush=True)
@@ -197,6 +197,19 @@ def test_ffi_full_size_tabulated_with_jitter_sampled_parity():
                             prf_q=9, jitter=jitter,
                             region=(y0 - cy0, y1 - cy0, x0 - cx0, x1 - cx0))
         parity.check_maps(snr[:, y0:y1, x0:x1].cpu().numpy(), flux[:, y0:y1, x0:x1].cpu().numpy(), ora)
+    # top-k: values equal the map's largest, and every fifth candidate
+    # matches the oracle at its own (trajectory, start pixel)
+    cands = tno.decode_candidates(o["topk"], res.n_topk)
+    tv = torch.topk(snr.reshape(-1), 100).values.cpu().numpy()
+    assert np.array_equal(np.array([c[0] for c in cands], np.float32), tv)
+    for c in cands[::5]:
+        _, _, j, y, x = c
+        cy0, cy1 = max(0, y - margin), min(H, y + 1 + margin)
+        cx0, cx1 = max(0, x - margin), min(W, x + 1 + margin)
+        ora = oracle.search(R[:, cy0:cy1, cx0:cx1].cpu().numpy(), sigma[cy0:cy1, cx0:cx1], times,
+                            t_ref, vel[j:j + 1], prf_kind=oracle.PRF_TABLE, stamp=5, prf_table=table,
+                            prf_q=9, jitter=jitter, region=(y - cy0, y + 1 - cy0, x - cx0, x + 1 - cx0))
+        parity.check_maps(np.array([[[c[0]]]], np.float32), np.array([[[c[1]]]], np.float32), ora)
 
 
 @pytest.mark.parametrize("kind,stamp", [(0, 5), (1, 7), ("table", 5), ("table", 7)])
