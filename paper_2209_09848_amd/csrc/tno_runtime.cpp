@@ -316,9 +316,15 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     // and share its windows in L2)
     set_search_shape(p, 0, DEFAULT_TBLOCK);
     p.ntiles_max = ((W + 63) / 64) * ((H + 15) / 16);
-    // search order: Morton (Z-order) code of the quantised velocity, so that
-    // trajectories adjacent in the work order have nearby shifts and their
-    // windows share cache lines
+    // search order: trajectories adjacent in the work order should have nearby
+    // shifts, so that the windows of a tile's co-resident blocks share cache
+    // lines.  Two candidate orders: the Morton (Z-order) code of the quantised
+    // velocity, and direction then speed.  Each is scored by the summed
+    // bounding box of the windows of every trajectory block at 8 times over
+    // the span (the footprint its blocks read together); the direction order
+    // is taken only when its footprint is smaller.  (Morton suits banks of
+    // many close speeds such as nested shells; a polar grid of few speeds over
+    // wide directions does better by direction.)
     {
         double vxmin = INFINITY, vxmax = -INFINITY, vymin = INFINITY, vymax = -INFINITY;
         for (int j = 0; j < p.J; ++j) {
@@ -340,6 +346,38 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
         p.perm.resize(p.J);
         std::iota(p.perm.begin(), p.perm.end(), 0);
         std::stable_sort(p.perm.begin(), p.perm.end(), [&](int32_t x, int32_t y) { return code[x] < code[y]; });
+        std::vector<int32_t> dir(p.J);
+        std::vector<double> ang(p.J), spd(p.J);
+        for (int j = 0; j < p.J; ++j) {
+            ang[j] = std::atan2(vel[2 * j + 1], vel[2 * j]);
+            spd[j] = std::hypot(vel[2 * j], vel[2 * j + 1]);
+        }
+        std::iota(dir.begin(), dir.end(), 0);
+        std::stable_sort(dir.begin(), dir.end(), [&](int32_t x, int32_t y) {
+            return ang[x] < ang[y] || (ang[x] == ang[y] && spd[x] < spd[y]);
+        });
+        const double wx = tno::search_tx(p.variant) + p.S - 1, wy = tno::search_ty(p.variant) + p.S - 1;
+        auto footprint = [&](const std::vector<int32_t> &ord) {
+            double area = 0.0;
+            for (int b0 = 0; b0 < p.J; b0 += p.tblock) {
+                const int b1 = std::min(p.J, b0 + p.tblock);
+                for (int i = 0; i < 8; ++i) {
+                    const double t = dtmin + (dtmax - dtmin) * i / 7.0;
+                    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+                    for (int m = b0; m < b1; ++m) {
+                        const double sx = vel[2 * ord[m]] * t, sy = vel[2 * ord[m] + 1] * t;
+                        x0 = std::min(x0, sx);
+                        x1 = std::max(x1, sx);
+                        y0 = std::min(y0, sy);
+                        y1 = std::max(y1, sy);
+                    }
+                    area += (wx + x1 - x0) * (wy + y1 - y0);
+                }
+            }
+            return area;
+        };
+        if (footprint(dir) < footprint(p.perm))
+            p.perm = dir;
     }
     p.jlist.clear();
     for (int o = 0; o < 2; ++o) {
