@@ -940,6 +940,15 @@ hipError_t autotune(tno_search *h, Request *q)
             (void)hipEventDestroy(x);
     if (e != hipSuccess)
         return e;
+    // the untuned default (first tile shape, blocks of 16) stays unless a
+    // candidate's probe beats it by more than 2 %: a short probe does not
+    // rank candidates that close reliably over the whole sequence
+    int def = 0;
+    for (size_t i = 0; i < cands.size(); ++i)
+        if (cands[i].v == 0 && cands[i].tb == std::min(DEFAULT_TBLOCK, p.J))
+            def = (int)i;
+    if (cands[best].ms > 0.98f * cands[def].ms)
+        best = def;
     set_search_shape(p, cands[best].v, cands[best].tb);
     const double rate = (double)p.J * p.H * p.W * probe / (cands[best].ms * 1e-3);
     h->tuned[shape_class(p)] = {cands[best].v, cands[best].tb, rate};
