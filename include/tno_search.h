@@ -58,7 +58,7 @@ extern "C" {
 /* PRF model (Sec. 2: PRF; Sec. 3.2: filter = trajectory line (x) PRF). */
 #define TNO_PRF_GAUSS_SAMPLED 0     /* exp(-(b-f)^2 / (2 s^2)) at pixel centres */
 #define TNO_PRF_GAUSS_INTEGRATED 1  /* Gaussian integrated over each pixel */
-#define TNO_PRF_TABLE 2             /* caller's tabulated PRF (Sec. 2.1: the share of a point
+#define TNO_PRF_TABLE 2             /* caller's tabulated PRF (Sec. 2: the share of a point
                                        source's flux each pixel records), not separable in
                                        general; read at the sub-pixel phase by bilinear
                                        interpolation (see tno_prf) */
@@ -136,7 +136,7 @@ typedef struct {
     int32_t top_k;               /* candidates wanted, 0..TNO_MAX_TOPK */
     const double *velocities;    /* [J][2] = (vx, vy) in pixels per unit of `times` */
     const double *jitter;        /* [T][2] = (theta_x, theta_y): pointing jitter of each frame
-                                    in pixels (Sec. 2.2, 3.1), added to the trail position of
+                                    in pixels (Sec. 2.1, 3.1), added to the trail position of
                                     every trajectory in that frame: v*(t_k - t_ref) + theta_k;
                                     finite, |theta| <= 256; NULL: none */
     int32_t sig_box;             /* 0: no significance map; else the odd side of the square
@@ -233,8 +233,31 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
 int tno_search_poll(tno_search *h, uint64_t ticket, int32_t timeout_ms, tno_result *out_result);
 
 /* Cancel pending work, free every device buffer, destroy the handle.
- * destroy(NULL) is a no-op. */
+ * Tickets still live are cancelled (nothing is copied back to host outputs;
+ * work already enqueued drains first).  destroy(NULL) is a no-op. */
 void tno_search_destroy(tno_search *h);
+
+/* Cancel a live ticket: its results are discarded.  Work already enqueued on
+ * the device runs to completion (device outputs may hold partial results);
+ * nothing is copied to host outputs.  The ticket's terminal poll then returns
+ * TNO_E_CANCELLED and releases its memory.  Returns TNO_OK, TNO_E_INVAL (NULL
+ * handle) or TNO_E_TICKET (unknown or collected ticket). */
+int tno_search_cancel(tno_search *h, uint64_t ticket);
+
+/* Memory and queue state of a handle (monitoring; not part of the method). */
+typedef struct {
+    uint64_t budget_bytes;       /* HBM budget of the handle */
+    uint64_t in_use_bytes;       /* device bytes charged to live requests and resident stacks */
+    uint64_t held_bytes;         /* recomputed sum of those blocks' sizes (equals in_use_bytes) */
+    uint64_t cached_bytes;       /* device blocks kept for reuse (in_use + cached <= budget) */
+    uint64_t device_allocs;      /* fresh device allocations attempted */
+    int32_t inflight;            /* tickets not yet collected */
+    int32_t resident_stacks;     /* stacks kept under a stack_key */
+    uint64_t reserved[4];
+} tno_stats;
+
+/* Fill *out with the handle's state.  Returns TNO_OK or TNO_E_INVAL. */
+int tno_search_stats(tno_search *h, tno_stats *out);
 
 /* Quantise an FP32 residual stack into reduced-precision codes with one
  * power-of-two scale per frame and 64x64 tile (the precision form's storage;

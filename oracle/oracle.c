@@ -18,7 +18,7 @@
  *     ivar(y,x)   = 1/sigma(y,x)^2 if sigma finite and > 0, else 0
  *                   (masked / clipped pixels, Sec. 3.2), 0 off the image
  *     D_k         = v * (t_k - t_ref) + theta_k           (per axis, FP64;
- *                   theta_k = pointing jitter of frame k, Sec. 2.2 / 3.1,
+ *                   theta_k = pointing jitter of frame k, Sec. 2.1 / 3.1,
  *                   folded into the filter as Sec. 3.2 says; 0 if absent)
  *     i_k         = floor(D_k + 1/2),  f_k = D_k - i_k    (anchor, phase)
  *   Gaussian PRF (separable):
@@ -26,7 +26,7 @@
  *              or = Phi((b+1/2-f)/sp) - Phi((b-1/2-f)/sp) (pixel-integrated)
  *     ghat        = g / sum_b g                           b = -h..h, S = 2h+1
  *     W_k(a,b)    = ghat(a; f_y,k) * ghat(b; f_x,k)       a = row, b = column
- *   Tabulated PRF (Sec. 2.1: the PRF gives the share of a point source's
+ *   Tabulated PRF (Sec. 2: the PRF gives the share of a point source's
  *   flux that each pixel records; not separable in general):
  *     P(u_y, u_x) = the share recorded by a pixel whose centre lies at offset
  *                   (u_y, u_x) from the source, tabulated on the grid

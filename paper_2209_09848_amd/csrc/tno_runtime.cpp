@@ -516,6 +516,7 @@ struct Request {
     uint64_t updates = 0;
     hipGraphExec_t exec = nullptr;   // graph mode: the executable graph this request ran
     std::string exec_key;
+    bool cancelled = false;          // tno_search_cancel: no outputs copied, poll gives CANCELLED
 };
 
 // Device arenas of finished requests, kept for reuse: a later request takes
@@ -528,6 +529,9 @@ struct ArenaCache {
     size_t held = 0;
     void *take(size_t bytes, size_t *got)
     {
+        // a cached block is already counted against the budget (as cached),
+        // so taking a larger one than asked for moves bytes from `held` to
+        // the taker's count without raising the total
         auto it = blocks.lower_bound(bytes);
         if (it == blocks.end() || it->first > 2 * bytes + (64u << 20))
             return nullptr;
@@ -563,7 +567,9 @@ struct tno_search {
     bool own_streams = false;
     unsigned next_stream = 0;
     uint64_t budget = 0;
-    uint64_t in_use = 0;               // live arenas + resident stacks
+    uint64_t in_use = 0;               // device blocks held by live requests and resident stacks
+                                       // (their actual sizes, so in_use + cache.held is what
+                                       // the handle holds on the device)
     int max_inflight = 64;
     uint64_t next_ticket = 1;
     uint64_t tick = 0;
@@ -583,6 +589,8 @@ struct tno_search {
     std::string arch;
     std::string tune_path;
     std::map<std::string, Tuned> tuned;
+    uint64_t n_alloc = 0;              // fresh device allocations attempted by get_block
+    uint64_t fault_alloc = 0;          // TNO_FAULT=alloc:N: the N-th attempt fails (0: never)
 
     void load_tuning()
     {
@@ -657,6 +665,8 @@ void *get_block(tno_search *h, size_t bytes, size_t *got)
     void *p = h->cache.take(bytes, got);
     if (p)
         return p;
+    if (++h->n_alloc == h->fault_alloc)
+        return nullptr;               // injected failure (TNO_FAULT=alloc:N)
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         h->cache.trim(0);
@@ -1030,7 +1040,7 @@ void release(tno_search *hd, Request *q)
         hd->free_execs.emplace(q->exec_key, q->exec);
     if (q->arena) {
         hd->cache.put(q->arena, q->arena_bytes);
-        hd->in_use -= q->plan.bytes;
+        hd->in_use -= q->arena_bytes;
     }
     if (q->stack) {
         q->stack->refs -= 1;
@@ -1162,6 +1172,13 @@ int tno_search_create(const tno_config *cfg, tno_search **out_handle)
         return hip_fail(e, "hipMemGetInfo", nullptr, 0);
     }
     h->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
+    if (const char *fe = getenv("TNO_FAULT")) {
+        // test hook: "alloc:N" makes the N-th fresh device allocation of this
+        // handle fail as if the device were out of memory
+        unsigned long long n = 0;
+        if (sscanf(fe, "alloc:%llu", &n) == 1)
+            h->fault_alloc = n;
+    }
     h->autotune = (cfg->flags & TNO_CFG_AUTOTUNE) != 0;
     h->graphs = (cfg->flags & TNO_CFG_GRAPHS) != 0;
     hipDeviceProp_t prop;
@@ -1286,7 +1303,7 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
         set_last(fail(TNO_E_NOMEM, "device allocation of %.3g GB failed", p.bytes / 1e9));
         return TNO_E_NOMEM;
     }
-    h->in_use += p.bytes;
+    h->in_use += q->arena_bytes;
     for (hipEvent_t &ev : q->ev)
         if ((e = hipEventCreate(&ev)) != hipSuccess) {
             release(h, q);
@@ -1313,7 +1330,7 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
         ns->dtype = p.dtype;
         ns->block = blk;
         ns->block_bytes = got;
-        ns->bytes = p.stack_bytes;
+        ns->bytes = got;
         ns->o_R = 0;
         ns->o_scales = align_up(rbytes, ALIGN);
         ns->o_sigma = ns->o_scales + align_up(sbytes, ALIGN);
@@ -1406,6 +1423,19 @@ int tno_search_poll(tno_search *h, uint64_t ticket, int32_t timeout_ms, tno_resu
             Request *q = it->second;
             (void)hipSetDevice(h->device);
             hipError_t e = hipEventQuery(q->ev[5]);
+            if (e == hipSuccess && q->cancelled) {
+                // the enqueued work has drained; nothing is copied back
+                tno_result res;
+                memset(&res, 0, sizeof res);
+                res.status = TNO_E_CANCELLED;
+                snprintf(res.message, sizeof res.message, "request cancelled");
+                res.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                                         q->t_submit).count();
+                h->live.erase(it);
+                release(h, q);
+                *out_result = res;
+                return TNO_E_CANCELLED;
+            }
             if (e == hipSuccess) {
                 tno_result res;
                 memset(&res, 0, sizeof res);
@@ -1465,6 +1495,45 @@ int tno_search_poll(tno_search *h, uint64_t ticket, int32_t timeout_ms, tno_resu
             return TNO_PENDING;
         std::this_thread::sleep_for(std::chrono::microseconds(50));
     }
+}
+
+int tno_search_cancel(tno_search *h, uint64_t ticket)
+{
+    if (!h) {
+        set_last(fail(TNO_E_INVAL, "handle is NULL"));
+        return TNO_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lock(h->mu);
+    auto it = h->live.find(ticket);
+    if (it == h->live.end()) {
+        set_last(fail(TNO_E_TICKET, "unknown or collected ticket %llu", (unsigned long long)ticket));
+        return TNO_E_TICKET;
+    }
+    it->second->cancelled = true;
+    return TNO_OK;
+}
+
+int tno_search_stats(tno_search *h, tno_stats *out)
+{
+    if (!h || !out) {
+        set_last(fail(TNO_E_INVAL, "handle or out is NULL"));
+        return TNO_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lock(h->mu);
+    memset(out, 0, sizeof *out);
+    out->budget_bytes = h->budget;
+    out->in_use_bytes = h->in_use;
+    out->cached_bytes = h->cache.held;
+    uint64_t held = 0;
+    for (auto &kv : h->live)
+        held += kv.second->arena_bytes;
+    for (auto &kv : h->stacks)
+        held += kv.second->block_bytes;
+    out->held_bytes = held;
+    out->inflight = (int32_t)h->live.size();
+    out->resident_stacks = (int32_t)h->stacks.size();
+    out->device_allocs = h->n_alloc;
+    return TNO_OK;
 }
 
 int tno_quantize(int32_t n_frames, int32_t height, int32_t width, int32_t dtype,

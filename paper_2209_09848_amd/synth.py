@@ -210,7 +210,7 @@ class TabulatedPSF:
     flux that a pixel whose centre lies at offset (dy, dx) from the source
     records (midpoint rule over sub x sub points per pixel).  With the default
     shape 49% of the flux lands in the peak pixel of a centred source and 87%
-    in the 2 x 2 pixels around a source on a pixel corner (Sec. 2.1 quotes
+    in the 2 x 2 pixels around a source on a pixel corner (Sec. 2 quotes
     about 50% and 90% for TESS)."""
 
     def __init__(self, core=(0.5, 0.38), angle_deg=35.0, halo_frac=0.15, halo_sigma=1.1,
@@ -249,7 +249,7 @@ class TabulatedPSF:
 def jitter_series(g: np.random.Generator, T: int, amp: float = 0.15) -> np.ndarray:
     """Per-frame pointing jitter [T][2] = (theta_x, theta_y) in pixels: a
     smoothed random walk per axis, scaled so its largest excursion is `amp`
-    (Sec. 2.2 shows up to +-0.15 px in Sector 5), referenced to frame 0."""
+    (Sec. 2.1 shows up to +-0.15 px in Sector 5), referenced to frame 0."""
     out = np.zeros((T, 2))
     for ax in range(2):
         w = np.cumsum(g.standard_normal(T))

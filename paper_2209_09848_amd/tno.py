@@ -112,9 +112,16 @@ class tno_refit_outputs(ctypes.Structure):
                 ("device_ms", ctypes.c_double)]
 
 
+class tno_stats(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("in_use_bytes", ctypes.c_uint64),
+                ("held_bytes", ctypes.c_uint64), ("cached_bytes", ctypes.c_uint64),
+                ("device_allocs", ctypes.c_uint64), ("inflight", ctypes.c_int32),
+                ("resident_stacks", ctypes.c_int32), ("reserved", ctypes.c_uint64 * 4)]
+
+
 EXPORTS = ("tno_search_create", "tno_search_submit", "tno_search_poll", "tno_search_destroy",
-           "tno_search_validate", "tno_search_footprint", "tno_search_last_error", "tno_quantize",
-           "tno_refit")
+           "tno_search_cancel", "tno_search_stats", "tno_search_validate", "tno_search_footprint",
+           "tno_search_last_error", "tno_quantize", "tno_refit")
 
 
 class TnoError(RuntimeError):
@@ -144,6 +151,10 @@ def load(path: str = LIB_PATH):
     lib.tno_search_poll.restype = ctypes.c_int
     lib.tno_search_destroy.argtypes = [_vp]
     lib.tno_search_destroy.restype = None
+    lib.tno_search_cancel.argtypes = [_vp, ctypes.c_uint64]
+    lib.tno_search_cancel.restype = ctypes.c_int
+    lib.tno_search_stats.argtypes = [_vp, P(tno_stats)]
+    lib.tno_search_stats.restype = ctypes.c_int
     lib.tno_search_validate.argtypes = [P(tno_request), P(tno_outputs), ctypes.c_char_p, ctypes.c_int32]
     lib.tno_search_validate.restype = ctypes.c_int
     lib.tno_search_footprint.argtypes = [P(tno_request), P(tno_outputs)]
@@ -188,6 +199,18 @@ def tno_search_poll(h, ticket: int, timeout_ms: int = -1):
 
 def tno_search_destroy(h) -> None:
     load().tno_search_destroy(h)
+
+
+def tno_search_cancel(h, ticket: int) -> int:
+    return int(load().tno_search_cancel(h, ctypes.c_uint64(ticket)))
+
+
+def tno_search_stats(h) -> tno_stats:
+    st = tno_stats()
+    rc = load().tno_search_stats(h, ctypes.byref(st))
+    if rc != TNO_OK:
+        raise TnoError(rc, tno_search_last_error())
+    return st
 
 
 def tno_search_validate(req: tno_request, out: tno_outputs):
@@ -289,6 +312,12 @@ class Search:
         if rc != TNO_OK:
             raise TnoError(rc, tno_search_last_error())
         return t
+
+    def cancel(self, ticket: int) -> int:
+        return tno_search_cancel(self.h, ticket)
+
+    def stats(self) -> tno_stats:
+        return tno_search_stats(self.h)
 
     def wait(self, ticket: int, timeout_ms: int = -1) -> tno_result:
         rc, res = tno_search_poll(self.h, ticket, timeout_ms)

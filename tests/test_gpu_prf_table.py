@@ -1,5 +1,5 @@
 """GPU parity of the tabulated (non-separable) PRF and the per-frame pointing
-jitter (Sec. 2.1, 2.2, 3.1 and 3.2: the filter is the jittered trajectory
+jitter (Sec. 2, 2.1, 3.1 and 3.2: the filter is the jittered trajectory
 line convolved with the PRF) against the FP64 oracle, element by element on
 small problems spanning several tiles and ragged edges, and on sampled start
 pixels at the full FFI size."""

@@ -372,6 +372,50 @@ def test_significance_interior_matches_uniform_filter(oracle_mod):
     np.testing.assert_allclose(got[h:-h, h:-h], (b / sd)[h:-h, h:-h], rtol=1e-9)
 
 
+@pytest.mark.parametrize("H,W,box", [(23, 31, 7), (17, 12, 63), (33, 45, 15), (9, 40, 21),
+                                      (28, 19, 255), (12, 12, 1)])
+def test_significance_whole_map_against_clipped_moments(oracle_mod, H, W, box):
+    """Whole map, edges included, against a construction that shares nothing
+    with the oracle's window loop: window sums of b and b^2 from
+    scipy.ndimage.uniform_filter with zero padding, divided by the clipped
+    window's pixel count (the same filter applied to ones), give the
+    population mean and variance of the clipped window.  Boxes wider than the
+    image and the one-pixel box (std 0 -> 0) are included."""
+    g = np.random.default_rng(7 * H + W + box)
+    b = g.standard_normal((H, W)) * (1 + g.random((H, W))) + 0.3
+    got = oracle_mod.significance(b, box)
+    ones = np.ones_like(b)
+    n = ndimage.uniform_filter(ones, box, mode="constant", cval=0.0)
+    s1 = ndimage.uniform_filter(b, box, mode="constant", cval=0.0) / n
+    s2 = ndimage.uniform_filter(b * b, box, mode="constant", cval=0.0) / n
+    var = np.maximum(s2 - s1 * s1, 0.0)
+    h = box // 2
+    cnt = np.array([[(min(H, y + h + 1) - max(0, y - h)) * (min(W, x + h + 1) - max(0, x - h))
+                     for x in range(W)] for y in range(H)], np.float64)
+    # the filter's count is the clipped window's size (a box of ones)
+    np.testing.assert_allclose(n * box * box, cnt, rtol=1e-12)
+    if box == 1:
+        assert np.all(got == 0.0)
+        return
+    ref = b / np.sqrt(var)
+    np.testing.assert_allclose(got, ref, rtol=1e-8, atol=1e-12)
+
+
+@pytest.mark.parametrize("H,W,box", [(14, 11, 5), (10, 13, 31)])
+def test_significance_whole_map_against_nan_padded_std(oracle_mod, H, W, box):
+    """Whole map against scipy.ndimage.generic_filter(np.nanstd) over a
+    NaN-padded image: the clipped window is the window with the off-image
+    samples left out (not zero-filled)."""
+    g = np.random.default_rng(H + 100 * W + box)
+    b = g.standard_normal((H, W)) * 2.0 - 0.7
+    got = oracle_mod.significance(b, box)
+    sd = ndimage.generic_filter(b, np.nanstd, size=box, mode="constant", cval=np.nan)
+    np.testing.assert_allclose(got, b / sd, rtol=1e-10)
+    # a zero-padded window would give a different, wrong answer at the edges
+    sd0 = ndimage.generic_filter(b, np.std, size=box, mode="constant", cval=0.0)
+    assert not np.allclose(got[0, :], (b / sd0)[0, :], rtol=1e-6)
+
+
 def test_significance_invariants(oracle_mod):
     g = np.random.default_rng(4)
     b = g.standard_normal((30, 30))

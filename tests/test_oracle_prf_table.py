@@ -1,5 +1,5 @@
-"""Pins of the oracle's tabulated PRF and pointing-jitter paths (Sec. 2.1:
-the PRF is the share of a point source's flux each pixel records; Sec. 2.2
+"""Pins of the oracle's tabulated PRF and pointing-jitter paths (Sec. 2:
+the PRF is the share of a point source's flux each pixel records; Sec. 2.1
 and 3.1: per-frame jitter theta_t of the pointing; Sec. 3.2: the filter is
 the trajectory line, jitter included, convolved with the PRF).
 
