@@ -82,6 +82,14 @@ extern "C" {
 /* tno_request.flags */
 #define TNO_REQ_DEVICE_PTRS 1u      /* every input and output pointer is device memory */
 #define TNO_REQ_VALIDATE 2u         /* also scan inputs for non-finite values */
+#define TNO_REQ_STAGE_FP32 4u       /* reduced-precision residuals: decode them into a
+                                       zero-padded FP32 copy (about T*(H+2P)*(W+2P)*4 bytes,
+                                       P the largest trail shift, up to 512) before the search,
+                                       which then runs faster.  Without this flag, stamps of
+                                       side 1, 3 and 5 with W % 4 == 0 and H*W*4 < 2^31 read
+                                       the codes in place (decoded, scaled and weighted while
+                                       each window is staged): no copy, a slower search.
+                                       FP32 residuals are always staged. */
 
 /* Largest stamp side accepted (odd). */
 #define TNO_MAX_STAMP 15

@@ -12,8 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtno_search.so")
-SOURCES = [os.path.join(CSRC, "tno_kernels.hip"), os.path.join(CSRC, "tno_refit.hip"),
-           os.path.join(CSRC, "tno_runtime.cpp")]
+SOURCES = [os.path.join(CSRC, "tno_kernels.hip"), os.path.join(CSRC, "tno_search_ws.hip"),
+           os.path.join(CSRC, "tno_refit.hip"), os.path.join(CSRC, "tno_runtime.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -8,22 +8,31 @@
 
 namespace tno {
 
-// Search tile shapes.  A lane owns CPL adjacent columns x RPL rows; a wave
-// spans 64*CPL columns; a block stacks NWAVE waves vertically.  Variant 0 is
-// the default; the others are autotuning candidates (stamp 5 only).
+// Search tile shapes.  A lane owns CPL adjacent columns x RPL rows; a block
+// stacks NWAVE waves vertically; the tile is TX start columns wide.
+// Variants 0-7 (k_search) read every window column a lane needs from LDS; a
+// wave spans 64*CPL columns.  Variant 8 (k_search_ws, stamps 1, 3 and 5)
+// reads only the lane's own two columns and takes its neighbours' columns
+// from the adjacent lanes by wave shifts, so the first and last lane of a
+// wave produce no output: 124 start columns per 128-column window.
 struct SearchVariant {
-    int nwave, cpl, rpl;
+    int nwave, cpl, rpl, tx;
     const char *name;
 };
 inline constexpr SearchVariant SEARCH_VARIANTS[] = {
-    {4, 2, 8, "w4c2"}, {8, 2, 8, "w8c2"}, {2, 2, 8, "w2c2"}, {4, 1, 8, "w4c1"},
-    {8, 1, 8, "w8c1"}, {4, 4, 8, "w4c4"}, {2, 2, 16, "w2c2r16"}, {4, 2, 16, "w4c2r16"},
+    {4, 2, 8, 128, "w4c2"}, {8, 2, 8, 128, "w8c2"}, {2, 2, 8, 128, "w2c2"}, {4, 1, 8, 64, "w4c1"},
+    {8, 1, 8, 64, "w8c1"}, {4, 4, 8, 256, "w4c4"}, {2, 2, 16, 128, "w2c2r16"}, {4, 2, 16, 128, "w4c2r16"},
+    {4, 2, 8, 124, "ws"}, {4, 2, 4, 124, "ws4"},
 };
-constexpr int N_SEARCH_VARIANTS = 8;
+constexpr int N_SEARCH_VARIANTS = 10;
+constexpr int SEARCH_WS = 8;             // the wave-shift variants: 8 and 4 rows per lane
+constexpr int SEARCH_WS4 = 9;
 constexpr int SEARCH_MAX_TX = 256;
 constexpr int SEARCH_MAX_TY = 64;
-__host__ __device__ constexpr int search_tx(int v) { return 64 * SEARCH_VARIANTS[v].cpl; }
+__host__ __device__ constexpr int search_tx(int v) { return SEARCH_VARIANTS[v].tx; }
 __host__ __device__ constexpr int search_ty(int v) { return SEARCH_VARIANTS[v].rpl * SEARCH_VARIANTS[v].nwave; }
+// Stamps the wave-shift variant serves (a lane's neighbours reach 2 columns).
+__host__ __device__ constexpr bool ws_stamp(int S) { return S == 1 || S == 3 || S == 5; }
 // Normaliser tile: 64 columns (1 per lane) x 128 rows (32 per lane, 4 waves).
 constexpr int LAMBDA_TX = 64;
 constexpr int LAMBDA_TY = 128;
@@ -69,6 +78,13 @@ struct TopkState {
 
 struct SearchArgs {
     const float4 *Z4;        // padded inverse-variance-weighted stack [T][Hp][Wp4] float4
+                             // (each group's columns in the order 4g, 4g+2, 4g+1, 4g+3);
+                             // NULL: read the caller's stack directly (R, scales,
+                             // ivar32 below; k_search_ws only)
+    const void *R;           // direct source: residuals [T][H][W] of `dtype`, W % 4 == 0
+    const float *scales;     // direct source: tile scales [T][nqy][nqx] (not F32)
+    const float *ivar32;     // direct source: ivar [H][W]
+    int dtype, nqy, nqx;
     const int32_t *tab32;    // [J][T][table_stride(S, sep)]
     const double *lam;       // [J][H][W]
     float *snr;              // [J][H][W]
@@ -130,6 +146,9 @@ hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a);
 // Variants 0..N_SEARCH_VARIANTS-1 for the separable stamp of side 5; variant 0
 // for every other (stamp, separability).
 hipError_t launch_search(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a);
+// The wave-shift search (variant SEARCH_WS) for stamps 1, 3 and 5, separable
+// or general, from Z or (Z4 NULL) directly from the caller's stack.
+hipError_t launch_search_ws(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a);
 hipError_t launch_trajmax(hipStream_t st, int J, int ntiles, int W, int HW,
                           const uint64_t *tile_keys, const float *snr, const float *flux,
                           void *traj_max_out);

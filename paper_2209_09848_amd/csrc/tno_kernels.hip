@@ -22,44 +22,12 @@
 #include <algorithm>
 
 #include "tno_internal.h"
+#include "tno_device.h"
 #include "../../include/tno_search.h"
 
 namespace tno {
 
 // ------------------------------------------------------------------ helpers
-
-typedef __attribute__((address_space(4))) int32_t cint32_t;   // constant address space
-typedef __attribute__((address_space(3))) float lfloat_t;      // LDS
-// Word 3 of a raw (unformatted, stride 0) buffer resource on gfx9-family GPUs.
-constexpr int BUF_DWORD3 = 0x00020000;
-
-__device__ __forceinline__ uint32_t ordered_key(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-__device__ __forceinline__ float key_to_float(uint32_t k)
-{
-    uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
-    return __uint_as_float(u);
-}
-
-// Work-item index of block b when items are dealt to the 8 XCDs in contiguous
-// ranges: consecutive blocks go round-robin to XCDs, so block b runs on XCD
-// b % 8; giving each XCD a contiguous item range keeps the trajectories of one
-// tile (which read the same frame region) on one XCD and its L2.
-__device__ __forceinline__ int xcd_item(int b, int nblocks)
-{
-    int per = nblocks >> 3;
-    return (b & 7) * per + (b >> 3);
-}
-
-__host__ static int xcd_grid(int n_items)
-{
-    int per = (n_items + 7) / 8;
-    return per * 8;
-}
 
 // ------------------------------------------------------------------ k_zero
 
@@ -116,16 +84,6 @@ hipError_t launch_ivar(hipStream_t st, int H, int W, const float *sigma, float *
 
 // ------------------------------------------------------------------ decode + k_prep_z
 
-__device__ __forceinline__ float decode_e4m3(uint32_t c)
-{
-    // E4M3fn code -> binary16 with the same sign/exponent/mantissa bits shifted
-    // into place: value(binary16) = value(E4M3) * 2^-8 for normals and
-    // subnormals alike; the caller's scale absorbs the 2^8.
-    uint16_t hb = (uint16_t)(((c & 0x80u) << 8) | ((c & 0x7Fu) << 7));
-    _Float16 hv;
-    __builtin_memcpy(&hv, &hb, 2);
-    return (float)hv;
-}
 
 template <int DT>
 __device__ __forceinline__ float load_residual(const void *R, const float *scales, size_t idx,
@@ -150,7 +108,7 @@ __device__ __forceinline__ float load_residual(const void *R, const float *scale
 
 // One thread per float4 group of the padded stack; grid (groups/256, Hp, T).
 // A group holds image columns 4g..4g+3 in the order (4g, 4g+2, 4g+1, 4g+3):
-// even columns first, so the search can stage a row's even and odd columns
+// even columns first, so that k_search can stage a row's even and odd columns
 // into separate halves with whole 8-byte stores.
 template <int DT>
 __global__ void k_prep_z(const void *__restrict__ R, const float *__restrict__ scales,
@@ -1011,6 +969,10 @@ static void launch_search_t(hipStream_t st, const SearchArgs &a)
 
 hipError_t launch_search(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a)
 {
+    if (variant == SEARCH_WS || variant == SEARCH_WS4)
+        return ws_stamp(S) ? launch_search_ws(st, S, sep, variant, a) : hipErrorInvalidValue;
+    if (!a.Z4)
+        return hipErrorInvalidValue;
     if (S == 5 && sep) {
         switch (variant) {
         case 0: launch_search_t<5, 4, 2>(st, a); break;

@@ -79,6 +79,10 @@ struct Plan {
     bool jitter = false;
     bool dev = false;
     int Pt = 0, Pb = 0, Pl = 0, Pr = 0, Hp = 0, Wp4 = 0;
+    // the search reads the caller's stack directly (decode x scale x ivar
+    // while staging) instead of a staged FP32 copy Z: reduced-precision
+    // storage, stamps 1/3/5, W a multiple of 4, one frame below 2^31 bytes
+    bool direct = false;
     std::vector<tno::TrailInfo> trail;
     int64_t n_colmeta = 0, n_kvals = 0;
     int ntx = 0, nty = 0, ntiles = 0;
@@ -171,7 +175,7 @@ Fail check_shape(const tno_request *r, const tno_outputs *o)
         return fail(TNO_E_INVAL, "max_detections > 0 needs outputs.detections");
     if ((o->significance || o->max_detections > 0) && r->sig_box == 0)
         return fail(TNO_E_INVAL, "significance outputs need sig_box > 0");
-    if ((r->flags & ~(TNO_REQ_DEVICE_PTRS | TNO_REQ_VALIDATE)) != 0)
+    if ((r->flags & ~(TNO_REQ_DEVICE_PTRS | TNO_REQ_VALIDATE | TNO_REQ_STAGE_FP32)) != 0)
         return fail(TNO_E_INVAL, "unknown request flags 0x%x", r->flags);
     if (!finite(r->t_ref) && !std::isnan(r->t_ref))
         return fail(TNO_E_INVAL, "t_ref must be finite or NaN");
@@ -188,6 +192,23 @@ Fail check_shape(const tno_request *r, const tno_outputs *o)
 
 // Tile shape of search variant v and trajectory-block size of the work order.
 constexpr int DEFAULT_TBLOCK = 16;
+
+// Whether search variant v is built for the plan's stamp: variant 0 serves
+// every stamp, the other k_search shapes the separable stamp of side 5, the
+// wave-shift variant stamps 1, 3 and 5 of either kind.
+bool variant_serves(const Plan &p, int v)
+{
+    if (v == tno::SEARCH_WS || v == tno::SEARCH_WS4)
+        return tno::ws_stamp(p.S);
+    if (p.direct)
+        return false;
+    return v == 0 || (v > 0 && v < tno::SEARCH_WS && p.S == 5 && p.sep);
+}
+
+bool direct_ok(const Plan &p)
+{
+    return tno::ws_stamp(p.S) && p.W % 4 == 0 && (double)p.H * p.W * 4.0 < 2147483647.0;
+}
 
 void set_search_shape(Plan &p, int v, int tblock)
 {
@@ -310,11 +331,16 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     p.Pr = std::min(PAD_CAP, std::max(0, gxmax) + h + tno::SEARCH_MAX_TX + 4);
     p.Hp = H + p.Pt + p.Pb;
     p.Wp4 = (int)(align_up((size_t)W + p.Pl + p.Pr, 4) / 4);
-    // untuned default: the first tile shape, trajectories in blocks of 16 (on
-    // the 100-trajectory FFI bank 2.7 % faster than one block of all, and
-    // blocks of 8 are 25 % slower: fewer trajectories of a tile run together
-    // and share its windows in L2)
-    set_search_shape(p, 0, DEFAULT_TBLOCK);
+    // reduced-precision stacks are searched in place (no FP32 copy) where
+    // the wave-shift search serves the stamp, unless the caller asks for the
+    // staged copy
+    p.direct = p.dtype != TNO_F32 && (r->flags & TNO_REQ_STAGE_FP32) == 0 && direct_ok(p);
+    // untuned default: the first tile shape (the wave-shift shape for a
+    // direct search), trajectories in blocks of 16 (on the 100-trajectory FFI
+    // bank 2.7 % faster than one block of all, and blocks of 8 are 25 %
+    // slower: fewer trajectories of a tile run together and share its windows
+    // in L2)
+    set_search_shape(p, p.direct ? tno::SEARCH_WS : 0, DEFAULT_TBLOCK);
     p.ntiles_max = ((W + 63) / 64) * ((H + 15) / 16);
     // search order: trajectories adjacent in the work order should have nearby
     // shifts, so that the windows of a tile's co-resident blocks share cache
@@ -451,7 +477,8 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
         if (!p.sep)
             p.o_prf = take((size_t)p.table_n * p.table_n * 8);
     }
-    p.o_Z = take(T * (size_t)p.Hp * p.Wp4 * 16);
+    if (!p.direct)
+        p.o_Z = take(T * (size_t)p.Hp * p.Wp4 * 16);
     p.o_iv32 = take(HW * 4);
     for (auto &L : p.lam)
         L.o_map = L.nj > 0 || &L == &p.lam[0] ? take((size_t)L.Hq * L.Wq * 8) : 0;
@@ -517,6 +544,8 @@ struct Request {
     hipGraphExec_t exec = nullptr;   // graph mode: the executable graph this request ran
     std::string exec_key;
     bool cancelled = false;          // tno_search_cancel: no outputs copied, poll gives CANCELLED
+    const void *src_R = nullptr;     // the residual stack on the device (set when enqueued)
+    const float *src_scales = nullptr;
 };
 
 // Device arenas of finished requests, kept for reuse: a later request takes
@@ -727,7 +756,13 @@ tno::SearchArgs search_args(const Request *q, float *snr, float *flux, int nfram
     const Plan &p = q->plan;
     void *A = q->arena;
     tno::SearchArgs sa;
-    sa.Z4 = at<float4>(A, p.o_Z);
+    sa.Z4 = p.direct ? nullptr : at<float4>(A, p.o_Z);
+    sa.R = q->src_R;
+    sa.scales = q->src_scales;
+    sa.ivar32 = at<float>(A, p.o_iv32);
+    sa.dtype = p.dtype;
+    sa.nqy = (p.H + TNO_QTILE - 1) / TNO_QTILE;
+    sa.nqx = (p.W + TNO_QTILE - 1) / TNO_QTILE;
     sa.tab32 = at<int32_t>(A, p.o_tab32);
     sa.lam = at<double>(A, p.o_lam);
     sa.snr = snr;
@@ -784,6 +819,8 @@ hipError_t enqueue_front(Request *q, const tno_request *r, bool events)
     void *A = q->arena;
     const Inputs in = inputs_of(q, r);
     hipError_t e;
+    q->src_R = in.R;
+    q->src_scales = in.scales;
     TRY(tno::launch_zero(st, at<int32_t>(A, p.o_err), 1));
     for (int o = 0; o < 2; ++o) {
         const auto &L = p.lam[o];
@@ -791,8 +828,9 @@ hipError_t enqueue_front(Request *q, const tno_request *r, bool events)
             TRY(tno::launch_ivar(st, p.H, p.W, in.sigma, o == 0 ? at<float>(A, p.o_iv32) : nullptr,
                                  at<double>(A, L.o_map), L.Hq, L.Wq, L.Pyt, L.Pxl, o, at<int32_t>(A, p.o_err)));
     }
-    TRY(tno::launch_prep_z(st, p.dtype, in.R, in.scales, at<float>(A, p.o_iv32), at<float4>(A, p.o_Z),
-                           p.T, p.H, p.W, p.Hp, p.Wp4, p.Pt, p.Pl));
+    if (!p.direct)
+        TRY(tno::launch_prep_z(st, p.dtype, in.R, in.scales, at<float>(A, p.o_iv32), at<float4>(A, p.o_Z),
+                               p.T, p.H, p.W, p.Hp, p.Wp4, p.Pt, p.Pl));
     if (events)
         TRY(hipEventRecord(q->ev[1], st));
     const tno::PrfSpec prf{p.kind, p.S, p.sigma_px, in.prf_tab, p.table_q};
@@ -892,8 +930,8 @@ std::string shape_class(const Plan &p)
 {
     auto lg = [](int v) { int b = 0; while ((1 << b) < v) ++b; return b; };
     char buf[64];
-    snprintf(buf, sizeof buf, "%s%d_H%d_W%d_J%d_T%d", p.sep ? "S" : "P", p.S, lg(p.H), lg(p.W), lg(p.J),
-             lg(p.T));
+    snprintf(buf, sizeof buf, "%s%s%d_H%d_W%d_J%d_T%d", p.direct ? "D" : "", p.sep ? "S" : "P", p.S, lg(p.H),
+             lg(p.W), lg(p.J), lg(p.T));
     return buf;
 }
 
@@ -908,14 +946,14 @@ hipError_t autotune(tno_search *h, Request *q)
         float ms;
     };
     std::vector<Cand> cands;
-    const int nv = (p.S == 5 && p.sep) ? tno::N_SEARCH_VARIANTS : 1;
     std::vector<int> tbs = {p.J};
     for (int tb : {64, 16})
         if (tb < p.J)
             tbs.push_back(tb);
-    for (int v = 0; v < nv; ++v)
-        for (int tb : tbs)
-            cands.push_back({v, tb, 0.0f});
+    for (int v = 0; v < tno::N_SEARCH_VARIANTS; ++v)
+        if (variant_serves(p, v))
+            for (int tb : tbs)
+                cands.push_back({v, tb, 0.0f});
     // the probe's frames are spread over the sequence (every kstride-th), so
     // that the trajectories' shifts spread as they do over the whole search
     const int probe = std::min(p.T, 48);
@@ -950,12 +988,13 @@ hipError_t autotune(tno_search *h, Request *q)
             (void)hipEventDestroy(x);
     if (e != hipSuccess)
         return e;
-    // the untuned default (first tile shape, blocks of 16) stays unless a
+    // the untuned default (its tile shape, blocks of 16) stays unless a
     // candidate's probe beats it by more than 2 %: a short probe does not
     // rank candidates that close reliably over the whole sequence
     int def = 0;
+    const int def_v = p.direct ? tno::SEARCH_WS : 0;
     for (size_t i = 0; i < cands.size(); ++i)
-        if (cands[i].v == 0 && cands[i].tb == std::min(DEFAULT_TBLOCK, p.J))
+        if (cands[i].v == def_v && cands[i].tb == std::min(DEFAULT_TBLOCK, p.J))
             def = (int)i;
     if (cands[best].ms > 0.98f * cands[def].ms)
         best = def;
@@ -978,10 +1017,10 @@ std::string graph_key(const Request *q)
                                      (o.best_snr != nullptr) << 4 | (o.best_traj != nullptr) << 5)
                                   : 0u;
     char buf[256];
-    snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %u", p.H, p.W, p.T,
-             p.J, p.S, (int)p.sep, p.kind, p.variant, p.tblock, p.dtype, p.k, p.box, p.kdet,
-             (int)p.own_snr, (int)p.own_flux, (int)p.dev, (int)p.jitter, p.Hp, p.Wp4, p.lam[0].nj > 0,
-             p.lam[1].nj > 0, copies);
+    snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %u", p.H, p.W,
+             p.T, p.J, p.S, (int)p.sep, p.kind, p.variant, p.tblock, p.dtype, p.k, p.box, p.kdet,
+             (int)p.own_snr, (int)p.own_flux, (int)p.dev, (int)p.jitter, (int)p.direct, p.Hp, p.Wp4,
+             p.lam[0].nj > 0, p.lam[1].nj > 0, copies);
     return buf;
 }
 
@@ -1384,7 +1423,7 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
     bool tune_now = false;
     {
         auto it = h->tuned.find(shape_class(q->plan));
-        if (it != h->tuned.end() && ((q->plan.S == 5 && q->plan.sep) || it->second.variant == 0))
+        if (it != h->tuned.end() && variant_serves(q->plan, it->second.variant))
             set_search_shape(q->plan, it->second.variant, it->second.tblock);
         else
             tune_now = h->autotune;

@@ -30,9 +30,10 @@ TNO_PRF_GAUSS_SAMPLED, TNO_PRF_GAUSS_INTEGRATED, TNO_PRF_TABLE = 0, 1, 2
 TNO_MAX_TABLE_Q = 64
 TNO_CFG_GRAPHS = 1
 TNO_CFG_AUTOTUNE = 2
-SEARCH_VARIANTS = ("w4c2", "w8c2", "w2c2", "w4c1", "w8c1", "w4c4", "w2c2r16", "w4c2r16")
+SEARCH_VARIANTS = ("w4c2", "w8c2", "w2c2", "w4c1", "w8c1", "w4c4", "w2c2r16", "w4c2r16", "ws", "ws4")
 TNO_REQ_DEVICE_PTRS = 1
 TNO_REQ_VALIDATE = 2
+TNO_REQ_STAGE_FP32 = 4
 TNO_MAX_TOPK = 1024
 TNO_MAX_DETECTIONS = 1024
 TNO_MAX_STAMP = 15
@@ -329,10 +330,12 @@ class Search:
         return res
 
 
-def shape_class(H, W, T, J, stamp=5, tabulated=False) -> str:
-    """Tuning-table key the library uses for a request shape."""
+def shape_class(H, W, T, J, stamp=5, tabulated=False, direct=False) -> str:
+    """Tuning-table key the library uses for a request shape; direct: a
+    reduced-precision stack searched in place (stamps 1, 3, 5; W % 4 == 0)."""
     lg = lambda v: max(0, (int(v) - 1).bit_length())
-    return "%s%d_H%d_W%d_J%d_T%d" % ("P" if tabulated else "S", stamp, lg(H), lg(W), lg(J), lg(T))
+    return "%s%s%d_H%d_W%d_J%d_T%d" % ("D" if direct else "", "P" if tabulated else "S", stamp, lg(H), lg(W),
+                                       lg(J), lg(T))
 
 
 def alloc_outputs(J, H, W, k, device="cuda", maps=True, detections=0):

@@ -115,6 +115,32 @@ def test_footprint_grows_with_bank_and_shift():
     assert tno.tno_search_footprint(req, out) > f2
 
 
+def test_reduced_precision_footprint_has_no_staged_fp32_copy():
+    """A reduced-precision stack searched in place (stamp 5, W % 4 == 0)
+    needs no padded FP32 copy of the stack: its footprint is smaller than the
+    FP32 request's by at least that copy (T*H*W*4 bytes) plus the halved
+    residuals; with a ragged width or a stamp of 7 the copy comes back."""
+    T, H, W = 40, 96, 128
+    f = {}
+    for name, dt, width, stamp in (("f32", tno.TNO_F32, W, 5), ("bf16", tno.TNO_BF16, W, 5),
+                                   ("fp8", tno.TNO_FP8_E4M3, W, 5), ("bf16_ragged", tno.TNO_BF16, W - 2, 5),
+                                   ("bf16_s7", tno.TNO_BF16, W, 7)):
+        req, out, keep = _host_request(H=H, W=width, T=T, J=4)
+        req.dtype = dt
+        req.prf = tno.tno_prf(0, stamp, 0.7)
+        sc = np.ones((T, (H + 63) // 64, (width + 63) // 64), np.float32)
+        keep.append(sc)
+        if dt != tno.TNO_F32:
+            req.tile_scales = sc.ctypes.data_as(ctypes.c_void_p)
+        f[name] = tno.tno_search_footprint(req, out)
+        assert f[name] > 0
+    copy = T * H * W * 4
+    assert f["f32"] - f["bf16"] >= copy + T * H * W * 2
+    assert f["bf16"] - f["fp8"] >= T * H * W - 64 * 1024
+    assert f["bf16_ragged"] > f["bf16"] + copy - T * H * 2 * 4
+    assert f["bf16_s7"] > f["bf16"] + copy
+
+
 def test_create_without_gpu_reports_device_error():
     import torch
     if torch.cuda.is_available():

@@ -49,7 +49,7 @@ def test_batched_shells_bf16_autotuned(tmp_path):
     lines = [l for l in cache.read_text().splitlines() if not l.startswith("#")]
     print("tuned:", lines, "first request %.1f ms (with tuning), then %.1f ms (search %.1f): %.3g updates/s"
           % (first, res.device_ms, res.search_ms, res.updates / (res.device_ms * 1e-3)), flush=True)
-    assert len(lines) == 1 and lines[0].split()[1] == tno.shape_class(H, W, T, J)
+    assert len(lines) == 1 and lines[0].split()[1] == tno.shape_class(H, W, T, J, direct=True)
     snr, flux = o["snr"], o["flux"]
     # reductions on the GPU's own maps
     best = snr.max(dim=0).values

@@ -192,16 +192,41 @@ def test_quantize_matches_oracle_codec_bit_exactly(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16", "fp8_e4m3"])
-def test_precision_search_parity_on_dequantized_values(dtype):
-    R, sigma, times, vel = _rand_problem(30, 12, 70, 140, 3)
+@pytest.mark.parametrize("case", [
+    (12, 70, 140, 3, 5, 20.0, None),       # searched in place (W % 4 == 0), several quantization tiles
+    (9, 37, 200, 2, 3, 60.0, None),        # stamp 3 in place; trails far off the image
+    (7, 33, 124, 2, 1, 20.0, None),        # stamp 1 in place, exactly one tile wide
+    (8, 45, 136, 3, 5, 20.0, "ws4"),       # in place, 4 rows per lane
+    (10, 40, 142, 2, 5, 20.0, None),       # W % 4 != 0: staged FP32 copy
+    (6, 41, 120, 2, 7, 20.0, None),        # stamp 7: staged FP32 copy
+    (12, 70, 140, 3, 5, 20.0, "stage"),    # staged FP32 copy on request
+])
+def test_precision_search_parity_on_dequantized_values(tmp_path, dtype, case):
+    T, H, W, J, stamp, vmax, variant = case
+    R, sigma, times, vel = _rand_problem(30 + W + stamp, T, H, W, J, vmax=vmax)
     codes, scales = codec.quantize(R, dtype)
     deq = codec.dequantize(codes, scales, dtype)
     ct = _to(codes.view(np.int16) if dtype != "fp8_e4m3" else codes)
-    print("precision case", dtype, flush=True)
-    o_, r_ = tno.search_tensors(ct, _to(sigma), _to(times), _to(vel), t_ref=float(times[0]),
-                                top_k=10, dtype=dtype, scales=_to(scales))
-    torch.cuda.synchronize()
-    o = oracle.search(deq, sigma, times, float(times[0]), vel)
+    print("precision case", dtype, case, flush=True)
+    handle = None
+    kw = {}
+    if variant == "stage":
+        kw["flags"] = tno.TNO_REQ_DEVICE_PTRS | tno.TNO_REQ_STAGE_FP32
+    elif variant:
+        direct = stamp in (1, 3, 5) and W % 4 == 0
+        path = tmp_path / "tune.txt"
+        path.write_text("%s %s %s %d 1.0\n" % (_arch(), tno.shape_class(H, W, T, J, stamp, direct=direct),
+                                               variant, J))
+        handle = tno.Search(0, tune_cache_path=str(path))
+    try:
+        o_, r_ = tno.search_tensors(ct, _to(sigma), _to(times), _to(vel), t_ref=float(times[0]), top_k=10,
+                                    dtype=dtype, scales=_to(scales), stamp=stamp, handle=handle, **kw)
+        torch.cuda.synchronize()
+    finally:
+        if handle:
+            handle.close()
+    assert r_.status == 0, r_.message
+    o = oracle.search(deq, sigma, times, float(times[0]), vel, stamp=stamp)
     parity.check_maps(o_["snr"].cpu().numpy(), o_["flux"].cpu().numpy(), o)
     parity.check_topk(tno.decode_candidates(o_["topk"], r_.n_topk), o["snr"], 10)
 
@@ -445,27 +470,67 @@ def _arch():
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
+def _forced(tmp_path, name, tb, H, W, T, J):
+    """A tuning cache that forces search variant `name` with trajectory
+    blocks of `tb` for problems of this shape class."""
+    path = tmp_path / ("tune_%s_%d.txt" % (name, tb))
+    path.write_text("%s %s %s %d 1.0\n" % (_arch(), tno.shape_class(H, W, T, J), name, tb))
+    return str(path)
+
+
 def test_every_tile_shape_and_block_gives_identical_bits(tmp_path):
-    """All search variants evaluate each output with the same operation order,
-    so forcing any (tile shape, trajectory block) through the tuning cache
-    must reproduce the default bits; one case also goes to the oracle."""
+    """The k_search shapes evaluate each output with the same operation
+    order, so forcing any (tile shape, trajectory block) through the tuning
+    cache reproduces the bits of the first shape; the wave-shift variants add
+    the horizontal taps in another order: they match the oracle and give
+    the same bits for both rows-per-lane shapes and every trajectory block."""
     R, sigma, times, vel = _rand_problem(80, 11, 70, 300, 5)
     T, H, W = R.shape
     J = vel.shape[0]
-    ref, _ = run_gpu(R, sigma, times, vel, float(times[0]), top_k=20)
     o = oracle.search(R, sigma, times, float(times[0]), vel)
-    parity.check_maps(ref["snr"], ref["flux"], o)
-    cls = tno.shape_class(H, W, T, J)
+    refs = {}
     for name in tno.SEARCH_VARIANTS:
+        fam = "ws" if name.startswith("ws") else "k_search"
         for tb in (J, 2):
-            path = tmp_path / ("tune_%s_%d.txt" % (name, tb))
-            path.write_text("%s %s %s %d 1.0\n" % (_arch(), cls, name, tb))
             print("variant", name, "tblock", tb, flush=True)
-            with tno.Search(0, tune_cache_path=str(path)) as h:
+            with tno.Search(0, tune_cache_path=_forced(tmp_path, name, tb, H, W, T, J)) as h:
                 g, res = run_gpu(R, sigma, times, vel, float(times[0]), top_k=20, handle=h)
+            if fam not in refs:
+                parity.check_maps(g["snr"], g["flux"], o)
+                refs[fam] = g
+                continue
+            ref = refs[fam]
             assert np.array_equal(g["snr"], ref["snr"]) and np.array_equal(g["flux"], ref["flux"])
             assert g["topk"] == ref["topk"]
             assert np.array_equal(g["best_traj"], ref["best_traj"])
+
+
+@pytest.mark.parametrize("variant", ["ws", "ws4"])
+@pytest.mark.parametrize("stamp,kind", [(1, 0), (3, 0), (5, 0), (5, 1), (3, "table"), (5, "table")])
+def test_wave_shift_variant_stamps_and_edges(tmp_path, stamp, kind, variant):
+    """The wave-shift search for every stamp it serves, separable and
+    tabulated, on an image narrower than one tile and one several tiles wide
+    with a ragged edge, trails leaving the frame: against the oracle."""
+    for (H, W, T, J, seed) in [(37, 50, 23, 3, 0), (70, 390, 41, 4, 1)]:
+        R, sigma, times, vel = _rand_problem(900 + seed + 10 * stamp, T, H, W, J)
+        vel = vel * 3.0                     # trails well off the image
+        if kind == "table":
+            q = 5
+            tab = synth.TabulatedPSF().table(stamp, q)
+            kw = dict(prf_kind=tno.TNO_PRF_TABLE, prf_table=_to(tab), prf_q=q, stamp=stamp)
+            okw = dict(prf_kind=oracle.PRF_TABLE, prf_table=tab, prf_q=q, stamp=stamp)
+        else:
+            kw = dict(prf_kind=kind, stamp=stamp)
+            okw = dict(prf_kind=kind, stamp=stamp)
+        print(variant, "stamp", stamp, "kind", kind, "shape", (T, H, W), "J", J, flush=True)
+        with tno.Search(0, tune_cache_path=_forced(tmp_path, variant, J, H, W, T, J)) as h:
+            g, res = tno.search_tensors(_to(R), _to(sigma), _to(times), _to(vel), t_ref=float(times[0]),
+                                        top_k=10, handle=h, **kw)
+        torch.cuda.synchronize()
+        assert res.status == 0, res.message
+        o = oracle.search(R, sigma, times, float(times[0]), vel, **okw)
+        parity.check_maps(g["snr"].cpu().numpy(), g["flux"].cpu().numpy(), o)
+        parity.check_topk(tno.decode_candidates(g["topk"], res.n_topk), o["snr"], 10)
 
 
 def test_autotune_writes_cache_and_keeps_results(tmp_path):
