@@ -342,6 +342,35 @@ int tno_search_validate(const tno_request *req, const tno_outputs *out, char *ms
  * internal buffers, outputs produced internally).  0 if the request is invalid. */
 uint64_t tno_search_footprint(const tno_request *req, const tno_outputs *out);
 
+/* Size of the fixed working array of tno_search_run_scratch (per GPU). */
+#define TNO_SCRATCH_BYTES (128ull << 20)
+
+/* For callers that cannot allocate device memory (code running under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the search
+ * of tno_search_submit + tno_search_poll as one synchronous call on `stream`
+ * (hipStream_t, NULL = the default stream) of the current device, with every
+ * intermediate buffer (staged stack, ivar maps, offset/weight table, trail
+ * kernels, normaliser, SNR/flux maps the caller does not take, tile keys,
+ * top-k state) placed in a fixed TNO_SCRATCH_BYTES array that the library's
+ * code object holds on each GPU it runs on, until the process ends.  No
+ * handle, no hipMalloc/hipFree and no allocating library call; the small
+ * inputs the plan needs (times, velocities, jitter) are read back to host
+ * memory, as tno_search_submit does.
+ *   req, out: as for tno_search_submit; TNO_REQ_DEVICE_PTRS is required, the
+ *             residuals are given (no stack_key), outputs are device memory.
+ *   out_result: filled on return (status, n_topk, updates, total_ms; the
+ *             per-phase times are 0).
+ * Returns TNO_OK; TNO_E_INVAL for an invalid request (as tno_search_validate)
+ * or without TNO_REQ_DEVICE_PTRS / with a stack_key; TNO_E_NOMEM when the
+ * request's working memory (tno_search_footprint minus the caller's buffers)
+ * exceeds TNO_SCRATCH_BYTES; TNO_E_DEVICE on a HIP error.  Calls on one GPU
+ * share its array: the library serialises the calls of one process on a GPU
+ * (a lock held for the whole call), and every buffer a search needs cleared is
+ * cleared by its kernels; calls from several processes each hold their own
+ * array.  Outputs are complete when the call returns. */
+int tno_search_run_scratch(const tno_request *req, const tno_outputs *out, void *stream,
+                           tno_result *out_result);
+
 /* Message of the last refused call on this thread (empty if none). */
 const char *tno_search_last_error(void);
 

@@ -1622,3 +1622,135 @@ void tno_search_destroy(tno_search *h)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- search without allocation
+//
+// tno_search_run_scratch: one synchronous search whose device working memory
+// (the plan's arena: staged stack, ivar maps, offset/weight table, trail
+// kernels, normaliser, maps the caller did not ask for, tile keys, top-k
+// state) is a fixed array in the library's code object instead of memory
+// allocated per request.  Requests whose arena exceeds it are refused.
+
+namespace {
+constexpr size_t SCRATCH_BYTES = TNO_SCRATCH_BYTES;
+constexpr int MAX_DEVICES = 64;
+}  // namespace
+
+// The array in device memory (one per GPU the library runs on).  In host code
+// its name is only a stand-in: the kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+namespace {
+
+struct ScratchSlot {
+    std::mutex mu;           // held for a whole call: calls on one GPU do not overlap
+    void *ptr = nullptr;     // the array's device address on this GPU
+};
+ScratchSlot g_scratch[MAX_DEVICES];
+
+// This device's address of `scratch` (looked up once per device, with the
+// device current); call with g_scratch[dev].mu held.
+hipError_t scratch_address(int dev, void **out)
+{
+    ScratchSlot &s = g_scratch[dev];
+    if (!s.ptr) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        s.ptr = p;
+    }
+    *out = s.ptr;
+    return hipSuccess;
+}
+
+}  // namespace
+
+int tno_search_run_scratch(const tno_request *req, const tno_outputs *out, void *stream, tno_result *out_result)
+{
+    if (!out_result) {
+        set_last(fail(TNO_E_INVAL, "out_result is NULL"));
+        return TNO_E_INVAL;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    tno_result res;
+    memset(&res, 0, sizeof res);
+    auto refuse = [&](const Fail &f) {
+        set_last(f);
+        res.status = f.code;
+        snprintf(res.message, sizeof res.message, "%s", f.msg);
+        *out_result = res;
+        return f.code;
+    };
+    Fail f = check_shape(req, out);
+    if (f.code)
+        return refuse(f);
+    if ((req->flags & TNO_REQ_DEVICE_PTRS) == 0)
+        return refuse(fail(TNO_E_INVAL, "tno_search_run_scratch needs TNO_REQ_DEVICE_PTRS"));
+    if (!req->residuals || req->stack_key != 0)
+        return refuse(fail(TNO_E_INVAL, "tno_search_run_scratch needs residuals and no stack_key"));
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= MAX_DEVICES)
+        return refuse(fail(TNO_E_DEVICE, "no usable current device (%s)", hipGetErrorString(e)));
+    // host copies of the small inputs the plan reads
+    std::vector<double> times_h((size_t)req->n_frames), vel_h((size_t)2 * req->n_traj), jit_h;
+    if ((e = hipMemcpy(times_h.data(), req->times, times_h.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(vel_h.data(), req->velocities, vel_h.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        return refuse(fail(TNO_E_DEVICE, "reading times/velocities: %s", hipGetErrorString(e)));
+    if (req->jitter) {
+        jit_h.resize((size_t)2 * req->n_frames);
+        if ((e = hipMemcpy(jit_h.data(), req->jitter, jit_h.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+            return refuse(fail(TNO_E_DEVICE, "reading jitter: %s", hipGetErrorString(e)));
+    }
+    Request q;
+    f = make_plan(req, out, times_h.data(), vel_h.data(), req->jitter ? jit_h.data() : nullptr, q.plan);
+    if (f.code)
+        return refuse(f);
+    const Plan &p = q.plan;
+    if (p.bytes > SCRATCH_BYTES)
+        return refuse(fail(TNO_E_NOMEM, "the request needs %zu bytes of working memory; "
+                                        "tno_search_run_scratch has %zu", p.bytes, SCRATCH_BYTES));
+    std::lock_guard<std::mutex> lock(g_scratch[dev].mu);
+    void *arena = nullptr;
+    if ((e = scratch_address(dev, &arena)) != hipSuccess)
+        return refuse(fail(TNO_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e)));
+    q.out = *out;
+    q.arena = arena;
+    q.arena_bytes = p.bytes;
+    q.stream = (hipStream_t)stream;
+    q.updates = (uint64_t)p.J * p.H * p.W * p.T;
+    // the host-side trail layout, search order and normaliser lists (the
+    // call waits for the stream before it returns, so the host vectors
+    // outlive the copies), then the request's kernels
+    hipStream_t st = q.stream;
+    if ((e = hipMemcpyAsync(at<void>(arena, p.o_trail), p.trail.data(), p.trail.size() * sizeof(tno::TrailInfo),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(at<void>(arena, p.o_perm), p.perm.data(), p.perm.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(at<void>(arena, p.o_jl), p.jlist.data(), p.jlist.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = enqueue_front(&q, req, false)) != hipSuccess || (e = enqueue_back(&q, false)) != hipSuccess) {
+        (void)hipStreamSynchronize(st);
+        return refuse(fail(TNO_E_DEVICE, "enqueue: %s", hipGetErrorString(e)));
+    }
+    if ((e = hipStreamSynchronize(st)) != hipSuccess)
+        return refuse(fail(TNO_E_DEVICE, "search: %s", hipGetErrorString(e)));
+    int32_t err = 0, counts[4] = {0, 0, 0, 0};
+    if ((e = hipMemcpy(&err, at<void>(arena, p.o_err), 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(counts, at<void>(arena, p.o_counts), 16, hipMemcpyDeviceToHost)) != hipSuccess)
+        return refuse(fail(TNO_E_DEVICE, "reading status: %s", hipGetErrorString(e)));
+    if (err & 1)
+        return refuse(fail(TNO_E_INTERNAL, "trail run exceeded its planned capacity"));
+    if (err & 2)
+        return refuse(fail(TNO_E_INVAL, "sigma so small that 1/sigma^2 overflows single precision"));
+    res.status = TNO_OK;
+    res.updates = q.updates;
+    res.n_topk = p.k;
+    res.n_above = counts[0];
+    res.n_detections = counts[1];
+    res.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out_result = res;
+    return TNO_OK;
+}

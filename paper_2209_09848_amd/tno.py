@@ -38,6 +38,7 @@ TNO_MAX_TOPK = 1024
 TNO_MAX_DETECTIONS = 1024
 TNO_MAX_STAMP = 15
 TNO_QTILE = 64
+TNO_SCRATCH_BYTES = 128 << 20
 
 DTYPE_CODE = {"f32": TNO_F32, "bf16": TNO_BF16, "f16": TNO_F16, "fp8_e4m3": TNO_FP8_E4M3}
 
@@ -122,7 +123,7 @@ class tno_stats(ctypes.Structure):
 
 EXPORTS = ("tno_search_create", "tno_search_submit", "tno_search_poll", "tno_search_destroy",
            "tno_search_cancel", "tno_search_stats", "tno_search_validate", "tno_search_footprint",
-           "tno_search_last_error", "tno_quantize", "tno_refit")
+           "tno_search_last_error", "tno_quantize", "tno_refit", "tno_search_run_scratch")
 
 
 class TnoError(RuntimeError):
@@ -162,6 +163,8 @@ def load(path: str = LIB_PATH):
     lib.tno_search_footprint.restype = ctypes.c_uint64
     lib.tno_search_last_error.argtypes = []
     lib.tno_search_last_error.restype = ctypes.c_char_p
+    lib.tno_search_run_scratch.argtypes = [P(tno_request), P(tno_outputs), _vp, P(tno_result)]
+    lib.tno_search_run_scratch.restype = ctypes.c_int
     lib.tno_quantize.argtypes = [ctypes.c_int32] * 4 + [_vp, _vp, _vp, _vp]
     lib.tno_quantize.restype = ctypes.c_int
     lib.tno_refit.argtypes = [P(tno_refit_request), P(tno_refit_outputs), _vp]
@@ -222,6 +225,16 @@ def tno_search_validate(req: tno_request, out: tno_outputs):
 
 def tno_search_footprint(req: tno_request, out: tno_outputs) -> int:
     return int(load().tno_search_footprint(ctypes.byref(req), ctypes.byref(out)))
+
+
+def tno_search_run_scratch(req: tno_request, out: tno_outputs, stream=None):
+    """The search as one synchronous call with no device allocation (its
+    working memory is the library's fixed per-GPU array of
+    TNO_SCRATCH_BYTES).  Returns (status, tno_result)."""
+    res = tno_result()
+    rc = int(load().tno_search_run_scratch(ctypes.byref(req), ctypes.byref(out),
+                                           ctypes.c_void_p(stream) if stream else None, ctypes.byref(res)))
+    return rc, res
 
 
 def tno_quantize(T, H, W, dtype, residuals_ptr, codes_ptr, scales_ptr, stream=None) -> int:

@@ -15,10 +15,14 @@ CLANG = "/opt/rocm/llvm/bin/clang++"
 @pytest.mark.skipif(not os.path.exists(CLANG), reason="ROCm clang not installed")
 def test_runtime_host_code_under_asan_ubsan(tmp_path):
     exe = str(tmp_path / "sanitize_driver")
+    # the runtime holds a device array (the scratch search's working memory),
+    # so it is compiled as HIP for gfx950; the sanitizers instrument host code only
     cmd = [CLANG, "-std=c++17", "-O1", "-g", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
            "-I" + os.path.join(ROOT, "include"),
-           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
-           os.path.join(ROOT, "tests", "host", "sanitize_driver.cpp"),
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+           "-x", "c++", os.path.join(ROOT, "tests", "host", "sanitize_driver.cpp"),
+           "-x", "hip", "--offload-arch=gfx950",
            os.path.join(ROOT, "paper_2209_09848_amd", "csrc", "tno_runtime.cpp"),
            "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
