@@ -78,6 +78,16 @@ extern "C" {
                                        stream pool or a non-default stream. */
 #define TNO_CFG_AUTOTUNE 2u         /* time the search's tile shapes and trajectory blocks on the
                                        first request of each shape class; keep the fastest */
+#define TNO_CFG_BATCH 4u            /* continuous batching: the search of every admitted request
+                                       is cut into chunks of its (tile, trajectory) work items;
+                                       steps -- single launches whose block ranges serve the
+                                       chunks of several requests -- run on two search streams,
+                                       at most two steps queued at a time, so a request admitted
+                                       while others run joins the next step.  Each request's
+                                       preparation and reductions run on its pool stream.
+                                       Results are bit-identical to unbatched requests.  Needs
+                                       the own stream pool (stream NULL) and excludes GRAPHS;
+                                       steps are formed whenever submit or poll is called. */
 
 /* tno_request.flags */
 #define TNO_REQ_DEVICE_PTRS 1u      /* every input and output pointer is device memory */
@@ -261,7 +271,10 @@ typedef struct {
     uint64_t device_allocs;      /* fresh device allocations attempted */
     int32_t inflight;            /* tickets not yet collected */
     int32_t resident_stacks;     /* stacks kept under a stack_key */
-    uint64_t reserved[4];
+    uint64_t batch_steps;        /* TNO_CFG_BATCH: search steps launched so far */
+    uint64_t batch_items;        /* TNO_CFG_BATCH: work items those steps covered */
+    uint64_t batch_shared;       /* TNO_CFG_BATCH: steps that served more than one request */
+    uint64_t reserved[1];
 } tno_stats;
 
 /* Fill *out with the handle's state.  Returns TNO_OK or TNO_E_INVAL. */

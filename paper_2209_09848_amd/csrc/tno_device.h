@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tno_internal.h"
+
 namespace tno {
 
 typedef __attribute__((address_space(4))) int32_t cint32_t;   // constant address space
@@ -31,6 +33,45 @@ __device__ __forceinline__ int xcd_item(int b, int nblocks)
 {
     int per = nblocks >> 3;
     return (b & 7) * per + (b >> 3);
+}
+
+// The request entry and work item of this block of a serving-loop step;
+// false for the padding blocks of an entry (its count is below nblk).
+// The step's tables are read-only for the whole launch: they are read through
+// the constant address space, so that the entry and the request's arguments
+// are scalar loads into scalar registers, as a single-request launch's are.
+// (The host compilation pass, which only parses device functions, takes the
+// plain reads: the address-space-qualified copies exist in device code only.)
+__device__ __forceinline__ StepEntry step_entry(const StepArgs &s, int r)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef __attribute__((address_space(4))) const StepEntry centry_t;
+    return ((centry_t *)s.ent)[r];
+#else
+    return s.ent[r];
+#endif
+}
+
+__device__ __forceinline__ SearchArgs step_args(const StepArgs &s, int r)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef __attribute__((address_space(4))) const SearchArgs cargs_t;
+    return ((cargs_t *)s.reqs)[r];
+#else
+    return s.reqs[r];
+#endif
+}
+
+__device__ __forceinline__ bool step_item(const StepArgs &s, int &r, int &item)
+{
+    const int b = blockIdx.x;
+    r = 0;
+    while (r + 1 < s.n && b >= step_entry(s, r + 1).begin)
+        ++r;
+    const StepEntry e = step_entry(s, r);
+    const int li = xcd_item(b - e.begin, e.nblk);
+    item = e.item0 + li;
+    return li < e.count;
 }
 
 __host__ inline int xcd_grid(int n_items)

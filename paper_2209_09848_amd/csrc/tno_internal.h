@@ -100,6 +100,20 @@ struct SearchArgs {
                              // tuning probe spreads its frames over the whole sequence)
 };
 
+// A step of the serving loop's search: one launch whose consecutive block
+// ranges work for different requests.  Entry r takes work items item0 ..
+// item0+count-1 of request r with blocks begin .. begin+nblk-1 (nblk a
+// multiple of 8, so that each entry's items are dealt to the XCDs in
+// contiguous ranges as a single-request launch deals them).
+struct StepEntry {
+    int32_t begin, nblk, item0, count;
+};
+struct StepArgs {
+    const SearchArgs *reqs;  // [n] the requests' search arguments (device memory)
+    const StepEntry *ent;    // [n] (device memory), by increasing begin
+    int n;
+};
+
 // One launch of the normaliser covers the trajectories of one storage
 // orientation; a transposed launch works in the transposed image (rows <->
 // columns) and writes Lam back in the image's own layout.
@@ -146,9 +160,16 @@ hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a);
 // Variants 0..N_SEARCH_VARIANTS-1 for the separable stamp of side 5; variant 0
 // for every other (stamp, separability).
 hipError_t launch_search(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a);
-// The wave-shift search (variant SEARCH_WS) for stamps 1, 3 and 5, separable
-// or general, from Z or (Z4 NULL) directly from the caller's stack.
-hipError_t launch_search_ws(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a);
+// One step of the serving loop over `nblocks` blocks; every request of the
+// step has the stamp, separability, variant and source kind (staged stack, or
+// the dtype read in place) of `proto`.
+hipError_t launch_search_step(hipStream_t st, int S, bool sep, int variant, const SearchArgs &proto,
+                              const StepArgs &step, int nblocks);
+// The wave-shift search (variants SEARCH_WS/SEARCH_WS4) for stamps 1, 3 and 5,
+// separable or general, from Z or (Z4 NULL) directly from the caller's stack;
+// with `step`, the serving loop's multi-request launch.
+hipError_t launch_search_ws(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a,
+                            const StepArgs *step = nullptr, int nblocks = 0);
 hipError_t launch_trajmax(hipStream_t st, int J, int ntiles, int W, int HW,
                           const uint64_t *tile_keys, const float *snr, const float *flux,
                           void *traj_max_out);

@@ -526,7 +526,7 @@ hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a)
 // Frame partials accumulate in FP32 over FRAME_CHUNK frames, then into FP64;
 // every form adds the terms of an output in the same order.
 template <int S, int NWAVE, int CPL, int RPL, bool SEP, bool XCH>
-__global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
+__device__ __forceinline__ void search_item(const SearchArgs &a, int item)
 {
     constexpr int h = S / 2;
     constexpr int NT = 64 * NWAVE;
@@ -547,9 +547,6 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
     __shared__ __align__(16) float win[XCH ? 1 : 2][NWIN * 4];
     __shared__ __align__(16) float xch[XCH ? 2 * NXR * TX : 1];
 
-    const int item = xcd_item(blockIdx.x, gridDim.x);
-    if (item >= a.n_items)
-        return;
     // work order: blocks of `tblock` velocity-sorted trajectories; within a
     // block the trajectory index runs fastest, then the tile
     const int ntiles = a.ntx * a.nty;
@@ -952,8 +949,28 @@ __global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
     }
 }
 
+// One request: block b takes work item xcd_item(b) of the request.
+template <int S, int NWAVE, int CPL, int RPL, bool SEP, bool XCH>
+__global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
+{
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item < a.n_items)
+        search_item<S, NWAVE, CPL, RPL, SEP, XCH>(a, item);
+}
+
+// A step of the serving loop: consecutive block ranges take work items of
+// different requests (step_item maps a block to its request and item).
+template <int S, int NWAVE, int CPL, int RPL, bool SEP, bool XCH>
+__global__ __launch_bounds__(64 * NWAVE) void k_search_step(StepArgs s)
+{
+    int r, item;
+    if (step_item(s, r, item))
+        search_item<S, NWAVE, CPL, RPL, SEP, XCH>(step_args(s, r), item);
+}
+
 template <int S, int NWAVE, int CPL, int RPL = 8, bool SEP = true>
-static void launch_search_t(hipStream_t st, const SearchArgs &a)
+static void launch_search_t(hipStream_t st, const SearchArgs &a, const StepArgs *step = nullptr,
+                            int nblocks = 0)
 {
     // the shared-row form wherever it applies, its LDS (one window, two
     // exchange buffers) keeps as many blocks per CU as two windows do, and the
@@ -963,26 +980,31 @@ static void launch_search_t(hipStream_t st, const SearchArgs &a)
     constexpr int LDS_2 = 2 * NWIN * 16;
     constexpr bool XCH = SEP && CPL % 2 == 0 && S > 1 && S - 1 <= RPL && NWAVE > 1 && NWAVE <= 4 &&
                          LDS_PER_CU / LDS_X >= LDS_PER_CU / LDS_2;
-    hipLaunchKernelGGL((k_search<S, NWAVE, CPL, RPL, SEP, XCH>), dim3(xcd_grid(a.n_items)),
-                       dim3(64 * NWAVE), 0, st, a);
+    if (step)
+        hipLaunchKernelGGL((k_search_step<S, NWAVE, CPL, RPL, SEP, XCH>), dim3(nblocks), dim3(64 * NWAVE), 0, st,
+                           *step);
+    else
+        hipLaunchKernelGGL((k_search<S, NWAVE, CPL, RPL, SEP, XCH>), dim3(xcd_grid(a.n_items)),
+                           dim3(64 * NWAVE), 0, st, a);
 }
 
-hipError_t launch_search(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a)
+static hipError_t launch_search_any(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a,
+                                    const StepArgs *step, int nblocks)
 {
     if (variant == SEARCH_WS || variant == SEARCH_WS4)
-        return ws_stamp(S) ? launch_search_ws(st, S, sep, variant, a) : hipErrorInvalidValue;
+        return ws_stamp(S) ? launch_search_ws(st, S, sep, variant, a, step, nblocks) : hipErrorInvalidValue;
     if (!a.Z4)
-        return hipErrorInvalidValue;
+        return hipErrorInvalidValue;   // k_search reads the staged stack only
     if (S == 5 && sep) {
         switch (variant) {
-        case 0: launch_search_t<5, 4, 2>(st, a); break;
-        case 1: launch_search_t<5, 8, 2>(st, a); break;
-        case 2: launch_search_t<5, 2, 2>(st, a); break;
-        case 3: launch_search_t<5, 4, 1>(st, a); break;
-        case 4: launch_search_t<5, 8, 1>(st, a); break;
-        case 5: launch_search_t<5, 4, 4>(st, a); break;
-        case 6: launch_search_t<5, 2, 2, 16>(st, a); break;
-        case 7: launch_search_t<5, 4, 2, 16>(st, a); break;
+        case 0: launch_search_t<5, 4, 2>(st, a, step, nblocks); break;
+        case 1: launch_search_t<5, 8, 2>(st, a, step, nblocks); break;
+        case 2: launch_search_t<5, 2, 2>(st, a, step, nblocks); break;
+        case 3: launch_search_t<5, 4, 1>(st, a, step, nblocks); break;
+        case 4: launch_search_t<5, 8, 1>(st, a, step, nblocks); break;
+        case 5: launch_search_t<5, 4, 4>(st, a, step, nblocks); break;
+        case 6: launch_search_t<5, 2, 2, 16>(st, a, step, nblocks); break;
+        case 7: launch_search_t<5, 4, 2, 16>(st, a, step, nblocks); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -991,29 +1013,42 @@ hipError_t launch_search(hipStream_t st, int S, bool sep, int variant, const Sea
         return hipErrorInvalidValue;
     if (sep) {
         switch (S) {
-        case 1: launch_search_t<1, 4, 2>(st, a); break;
-        case 3: launch_search_t<3, 4, 2>(st, a); break;
-        case 7: launch_search_t<7, 4, 2>(st, a); break;
-        case 9: launch_search_t<9, 4, 2>(st, a); break;
-        case 11: launch_search_t<11, 4, 2>(st, a); break;
-        case 13: launch_search_t<13, 4, 2>(st, a); break;
-        case 15: launch_search_t<15, 4, 2>(st, a); break;
+        case 1: launch_search_t<1, 4, 2>(st, a, step, nblocks); break;
+        case 3: launch_search_t<3, 4, 2>(st, a, step, nblocks); break;
+        case 7: launch_search_t<7, 4, 2>(st, a, step, nblocks); break;
+        case 9: launch_search_t<9, 4, 2>(st, a, step, nblocks); break;
+        case 11: launch_search_t<11, 4, 2>(st, a, step, nblocks); break;
+        case 13: launch_search_t<13, 4, 2>(st, a, step, nblocks); break;
+        case 15: launch_search_t<15, 4, 2>(st, a, step, nblocks); break;
         default: return hipErrorInvalidValue;
         }
     } else {
         switch (S) {
-        case 1: launch_search_t<1, 4, 2, 8, false>(st, a); break;
-        case 3: launch_search_t<3, 4, 2, 8, false>(st, a); break;
-        case 5: launch_search_t<5, 4, 2, 8, false>(st, a); break;
-        case 7: launch_search_t<7, 4, 2, 8, false>(st, a); break;
-        case 9: launch_search_t<9, 4, 2, 8, false>(st, a); break;
-        case 11: launch_search_t<11, 4, 2, 8, false>(st, a); break;
-        case 13: launch_search_t<13, 4, 2, 8, false>(st, a); break;
-        case 15: launch_search_t<15, 4, 2, 8, false>(st, a); break;
+        case 1: launch_search_t<1, 4, 2, 8, false>(st, a, step, nblocks); break;
+        case 3: launch_search_t<3, 4, 2, 8, false>(st, a, step, nblocks); break;
+        case 5: launch_search_t<5, 4, 2, 8, false>(st, a, step, nblocks); break;
+        case 7: launch_search_t<7, 4, 2, 8, false>(st, a, step, nblocks); break;
+        case 9: launch_search_t<9, 4, 2, 8, false>(st, a, step, nblocks); break;
+        case 11: launch_search_t<11, 4, 2, 8, false>(st, a, step, nblocks); break;
+        case 13: launch_search_t<13, 4, 2, 8, false>(st, a, step, nblocks); break;
+        case 15: launch_search_t<15, 4, 2, 8, false>(st, a, step, nblocks); break;
         default: return hipErrorInvalidValue;
         }
     }
     return hipGetLastError();
+}
+
+hipError_t launch_search(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a)
+{
+    return launch_search_any(st, S, sep, variant, a, nullptr, 0);
+}
+
+hipError_t launch_search_step(hipStream_t st, int S, bool sep, int variant, const SearchArgs &proto,
+                              const StepArgs &step, int nblocks)
+{
+    if (nblocks <= 0 || step.n <= 0)
+        return hipErrorInvalidValue;
+    return launch_search_any(st, S, sep, variant, proto, &step, nblocks);
 }
 
 // ------------------------------------------------------------------ reductions

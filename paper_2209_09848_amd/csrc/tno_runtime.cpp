@@ -16,6 +16,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <fstream>
 #include <map>
 #include <numeric>
@@ -546,6 +547,11 @@ struct Request {
     bool cancelled = false;          // tno_search_cancel: no outputs copied, poll gives CANCELLED
     const void *src_R = nullptr;     // the residual stack on the device (set when enqueued)
     const float *src_scales = nullptr;
+    // TNO_CFG_BATCH: end of the preparation on `stream`, and the next search
+    // work item not yet handed to a step
+    hipEvent_t prep_done = nullptr;
+    int next_item = 0;
+    bool end_recorded = false;       // ev[5] recorded (a batched request records it late)
 };
 
 // Device arenas of finished requests, kept for reuse: a later request takes
@@ -589,6 +595,11 @@ struct ArenaCache {
 }  // namespace
 
 constexpr int STREAM_POOL = 4;   // at the default priority
+// TNO_CFG_BATCH: step size (blocks), requests per step, step descriptor slots
+constexpr int STEP_BLOCKS = 8192;
+constexpr int STEP_ENTRIES = 32;
+constexpr int STEP_SLOTS = 4;
+constexpr int STEP_CHUNK_MIN = 1024;   // smallest chunk a request gets in a shared step
 
 struct tno_search {
     int device = 0;
@@ -620,6 +631,20 @@ struct tno_search {
     std::map<std::string, Tuned> tuned;
     uint64_t n_alloc = 0;              // fresh device allocations attempted by get_block
     uint64_t fault_alloc = 0;          // TNO_FAULT=alloc:N: the N-th attempt fails (0: never)
+    // TNO_CFG_BATCH: requests whose search items are not all launched (FIFO),
+    // the two search streams, and the step descriptor slots (device table +
+    // pinned host staging, busy until the step's event completes)
+    bool batch = false;
+    std::deque<Request *> ready;
+    hipStream_t sstream[2] = {nullptr, nullptr};
+    unsigned next_sstream = 0;
+    struct StepSlot {
+        void *dev = nullptr;
+        void *host = nullptr;
+        hipEvent_t done = nullptr;
+        bool busy = false;
+    } slots[STEP_SLOTS];
+    uint64_t n_steps = 0, n_step_items = 0, n_shared = 0;
 
     void load_tuning()
     {
@@ -873,7 +898,22 @@ hipError_t enqueue_front(Request *q, const tno_request *r, bool events)
 
 // Enqueue the numerator search, the reductions and the output copies;
 // `events`: record the phase boundaries and the end event.
+hipError_t enqueue_reduce(Request *q, bool events);
+
 hipError_t enqueue_back(Request *q, bool events)
+{
+    const Plan &p = q->plan;
+    hipError_t e;
+    const tno::SearchArgs sa = search_args(q, snr_map(q), flux_map(q), p.T);
+    TRY(tno::launch_search(q->stream, p.S, p.sep, p.variant, sa));
+    if (events)
+        TRY(hipEventRecord(q->ev[4], q->stream));
+    return enqueue_reduce(q, events);
+}
+
+// The reductions and output copies after the search (on the request's
+// stream); `events`: record the end event.
+hipError_t enqueue_reduce(Request *q, bool events)
 {
     const Plan &p = q->plan;
     hipStream_t st = q->stream;
@@ -881,11 +921,8 @@ hipError_t enqueue_back(Request *q, bool events)
     float *snr = snr_map(q);
     float *flux = flux_map(q);
     const int HW = p.H * p.W;
-    hipError_t e;
     const tno::SearchArgs sa = search_args(q, snr, flux, p.T);
-    TRY(tno::launch_search(st, p.S, p.sep, p.variant, sa));
-    if (events)
-        TRY(hipEventRecord(q->ev[4], st));
+    hipError_t e;
     TRY(tno::launch_trajmax(st, p.J, p.ntiles, p.W, HW, sa.tile_keys, snr, flux, at<void>(A, p.o_tmax)));
     TRY(tno::launch_best(st, p.J, HW, snr, at<float>(A, p.o_best), at<int32_t>(A, p.o_bestj)));
     if (p.k > 0)
@@ -921,6 +958,7 @@ hipError_t enqueue_back(Request *q, bool events)
     }
     if (events)
         TRY(hipEventRecord(q->ev[5], st));
+    q->end_recorded = q->end_recorded || events;
     return hipSuccess;
 }
 
@@ -1069,9 +1107,111 @@ hipError_t run_graphed(tno_search *h, Request *q, const tno_request *req)
     q->exec_key = key;
     if ((e = hipGraphLaunch(x, q->stream)) != hipSuccess)
         return e;
+    q->end_recorded = true;
     return hipEventRecord(q->ev[5], q->stream);
 }
 #undef TRY
+
+// TNO_CFG_BATCH: form and launch search steps while fewer than two are
+// queued.  A step takes the oldest ready request (preparation finished)
+// with search items left and every other ready request of the same kernel
+// (stamp, separability, tile shape, source kind), gives each a chunk of its
+// items in request order (an equal share of STEP_BLOCKS, at least
+// STEP_CHUNK_MIN), copies the requests' arguments and chunk table into a free
+// descriptor slot and launches once on the next search stream.  The stream
+// of every request in the step waits for the step; a request whose last
+// items were launched gets its reductions queued there.  Cancelled requests
+// leave the queue with their end event recorded after their launched steps.
+// Called with the handle's lock held.
+hipError_t pump(tno_search *h)
+{
+    hipError_t e = hipSuccess;
+    for (;;) {
+        int nbusy = 0, slot = -1;
+        for (int i = 0; i < STEP_SLOTS; ++i) {
+            auto &sl = h->slots[i];
+            if (sl.busy && hipEventQuery(sl.done) == hipSuccess)
+                sl.busy = false;
+            if (sl.busy)
+                ++nbusy;
+            else if (slot < 0)
+                slot = i;
+        }
+        // drop cancelled requests from the queue
+        for (auto it = h->ready.begin(); it != h->ready.end();) {
+            Request *q = *it;
+            if (!q->cancelled) {
+                ++it;
+                continue;
+            }
+            if ((e = hipEventRecord(q->ev[5], q->stream)) != hipSuccess)
+                return e;
+            q->end_recorded = true;
+            it = h->ready.erase(it);
+        }
+        if (nbusy >= 2 || slot < 0 || h->ready.empty())
+            return hipSuccess;
+        // the requests this step serves
+        std::vector<Request *> take;
+        const Plan *cls = nullptr;
+        for (Request *q : h->ready) {
+            if (hipEventQuery(q->prep_done) != hipSuccess)
+                continue;
+            const Plan &p = q->plan;
+            if (cls && (p.S != cls->S || p.sep != cls->sep || p.variant != cls->variant ||
+                        p.direct != cls->direct || (p.direct && p.dtype != cls->dtype)))
+                continue;
+            if (!cls)
+                cls = &p;
+            take.push_back(q);
+            if ((int)take.size() == STEP_ENTRIES)
+                break;
+        }
+        if (take.empty())
+            return hipSuccess;
+        const int share = std::max(STEP_CHUNK_MIN, (STEP_BLOCKS / (int)take.size() + 7) / 8 * 8);
+        auto &sl = h->slots[slot];
+        tno::SearchArgs *args = (tno::SearchArgs *)sl.host;
+        tno::StepEntry *ent = (tno::StepEntry *)((char *)sl.host + STEP_ENTRIES * sizeof(tno::SearchArgs));
+        int n = 0, nblocks = 0;
+        for (Request *q : take) {
+            const Plan &p = q->plan;
+            const int n_items = p.ntiles * p.J;
+            const int cnt = std::min(share, n_items - q->next_item);
+            args[n] = search_args(q, snr_map(q), flux_map(q), p.T);
+            ent[n] = {nblocks, (cnt + 7) / 8 * 8, q->next_item, cnt};
+            nblocks += ent[n].nblk;
+            ++n;
+        }
+        hipStream_t ss = h->sstream[h->next_sstream++ & 1];
+        tno::StepArgs sa;
+        sa.reqs = (const tno::SearchArgs *)sl.dev;
+        sa.ent = (const tno::StepEntry *)((char *)sl.dev + STEP_ENTRIES * sizeof(tno::SearchArgs));
+        sa.n = n;
+        const size_t bytes = STEP_ENTRIES * (sizeof(tno::SearchArgs) + sizeof(tno::StepEntry));
+        const Plan &p0 = take[0]->plan;
+        if ((e = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, ss)) != hipSuccess ||
+            (e = tno::launch_search_step(ss, p0.S, p0.sep, p0.variant, args[0], sa, nblocks)) != hipSuccess ||
+            (e = hipEventRecord(sl.done, ss)) != hipSuccess)
+            return e;
+        sl.busy = true;
+        h->n_steps += 1;
+        h->n_shared += n > 1;
+        for (int i = 0; i < n; ++i) {
+            Request *q = take[i];
+            q->next_item += ent[i].count;
+            h->n_step_items += ent[i].count;
+            if ((e = hipStreamWaitEvent(q->stream, sl.done, 0)) != hipSuccess)
+                return e;
+            if (q->next_item == q->plan.ntiles * q->plan.J) {
+                h->ready.erase(std::find(h->ready.begin(), h->ready.end(), q));
+                if ((e = hipEventRecord(q->ev[4], q->stream)) != hipSuccess ||
+                    (e = enqueue_reduce(q, true)) != hipSuccess)
+                    return e;
+            }
+        }
+    }
+}
 
 void release(tno_search *hd, Request *q)
 {
@@ -1088,6 +1228,8 @@ void release(tno_search *hd, Request *q)
     for (hipEvent_t &e : q->ev)
         if (e)
             (void)hipEventDestroy(e);
+    if (q->prep_done)
+        (void)hipEventDestroy(q->prep_done);
     delete q;
 }
 
@@ -1172,6 +1314,14 @@ int tno_search_create(const tno_config *cfg, tno_search **out_handle)
         set_last(fail(TNO_E_INVAL, "config.reserved must be 0"));
         return TNO_E_INVAL;
     }
+    if ((cfg->flags & ~(TNO_CFG_GRAPHS | TNO_CFG_AUTOTUNE | TNO_CFG_BATCH)) != 0) {
+        set_last(fail(TNO_E_INVAL, "unknown config flags 0x%x", cfg->flags));
+        return TNO_E_INVAL;
+    }
+    if ((cfg->flags & TNO_CFG_BATCH) && (cfg->stream || (cfg->flags & TNO_CFG_GRAPHS))) {
+        set_last(fail(TNO_E_INVAL, "TNO_CFG_BATCH needs the own stream pool and excludes TNO_CFG_GRAPHS"));
+        return TNO_E_INVAL;
+    }
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || cfg->device < 0 || cfg->device >= ndev) {
@@ -1220,6 +1370,22 @@ int tno_search_create(const tno_config *cfg, tno_search **out_handle)
     }
     h->autotune = (cfg->flags & TNO_CFG_AUTOTUNE) != 0;
     h->graphs = (cfg->flags & TNO_CFG_GRAPHS) != 0;
+    h->batch = (cfg->flags & TNO_CFG_BATCH) != 0;
+    if (h->batch) {
+        const size_t bytes = STEP_ENTRIES * (sizeof(tno::SearchArgs) + sizeof(tno::StepEntry));
+        for (int i = 0; i < 2 && e == hipSuccess; ++i)
+            e = hipStreamCreateWithFlags(&h->sstream[i], hipStreamNonBlocking);
+        for (int i = 0; i < STEP_SLOTS && e == hipSuccess; ++i) {
+            auto &sl = h->slots[i];
+            if ((e = hipMalloc(&sl.dev, bytes)) == hipSuccess && (e = hipHostMalloc(&sl.host, bytes, 0)) == hipSuccess)
+                e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        }
+        if (e != hipSuccess) {
+            const int rc = hip_fail(e, "creating the batching streams and step slots", nullptr, 0);
+            tno_search_destroy(h);
+            return rc;
+        }
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, cfg->device) == hipSuccess) {
         h->arch = prop.gcnArchName;
@@ -1428,11 +1594,23 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
         else
             tune_now = h->autotune;
     }
-    if (h->graphs && !tune_now)
+    if (h->graphs && !tune_now) {
         e = run_graphed(h, q, req);
-    else if ((e = enqueue_pre(q)) == hipSuccess && (e = enqueue_front(q, req, true)) == hipSuccess &&
-             (!tune_now || (e = autotune(h, q)) == hipSuccess))
+    } else if (h->batch && !tune_now) {
+        // the preparation now; the search joins the next steps (pump)
+        if ((e = enqueue_pre(q)) == hipSuccess && (e = enqueue_front(q, req, true)) == hipSuccess &&
+            (e = hipEventCreateWithFlags(&q->prep_done, hipEventDisableTiming)) == hipSuccess &&
+            (e = hipEventRecord(q->prep_done, q->stream)) == hipSuccess) {
+            q->next_item = 0;
+            h->ready.push_back(q);
+            e = pump(h);
+            if (e != hipSuccess)
+                h->ready.erase(std::find(h->ready.begin(), h->ready.end(), q));
+        }
+    } else if ((e = enqueue_pre(q)) == hipSuccess && (e = enqueue_front(q, req, true)) == hipSuccess &&
+               (!tune_now || (e = autotune(h, q)) == hipSuccess)) {
         e = enqueue_back(q, true);
+    }
     if (e != hipSuccess) {
         (void)hipStreamSynchronize(q->stream);
         release(h, q);
@@ -1461,7 +1639,16 @@ int tno_search_poll(tno_search *h, uint64_t ticket, int32_t timeout_ms, tno_resu
             }
             Request *q = it->second;
             (void)hipSetDevice(h->device);
-            hipError_t e = hipEventQuery(q->ev[5]);
+            if (h->batch) {
+                hipError_t ep = pump(h);
+                if (ep != hipSuccess) {
+                    set_last(fail(TNO_E_DEVICE, "search step: %s", hipGetErrorString(ep)));
+                    return TNO_E_DEVICE;
+                }
+            }
+            // (a batched request's end event is recorded once its last
+            // search step is launched: pending until then)
+            hipError_t e = q->end_recorded ? hipEventQuery(q->ev[5]) : hipErrorNotReady;
             if (e == hipSuccess && q->cancelled) {
                 // the enqueued work has drained; nothing is copied back
                 tno_result res;
@@ -1572,6 +1759,9 @@ int tno_search_stats(tno_search *h, tno_stats *out)
     out->inflight = (int32_t)h->live.size();
     out->resident_stacks = (int32_t)h->stacks.size();
     out->device_allocs = h->n_alloc;
+    out->batch_steps = h->n_steps;
+    out->batch_items = h->n_step_items;
+    out->batch_shared = h->n_shared;
     return TNO_OK;
 }
 
@@ -1598,8 +1788,12 @@ void tno_search_destroy(tno_search *h)
     {
         std::lock_guard<std::mutex> lock(h->mu);
         (void)hipSetDevice(h->device);
+        for (hipStream_t s : h->sstream)
+            if (s)
+                (void)hipStreamSynchronize(s);
         for (hipStream_t s : h->streams)
             (void)hipStreamSynchronize(s);
+        h->ready.clear();
         for (auto &kv : h->live)
             release(h, kv.second);
         h->live.clear();
@@ -1617,6 +1811,17 @@ void tno_search_destroy(tno_search *h)
         if (h->own_streams)
             for (hipStream_t s : h->streams)
                 (void)hipStreamDestroy(s);
+        for (hipStream_t s : h->sstream)
+            if (s)
+                (void)hipStreamDestroy(s);
+        for (auto &sl : h->slots) {
+            if (sl.dev)
+                (void)hipFree(sl.dev);
+            if (sl.host)
+                (void)hipHostFree(sl.host);
+            if (sl.done)
+                (void)hipEventDestroy(sl.done);
+        }
     }
     delete h;
 }

@@ -191,7 +191,7 @@ __device__ __forceinline__ float4 decode_group(const Raw<SRC> &g)
 }  // namespace
 
 template <int S, bool SEP, int SRC, int RPL>
-__global__ __launch_bounds__(64 * WS_NWAVE) __attribute__((amdgpu_waves_per_eu(4))) void k_search_ws(SearchArgs a)
+__device__ __forceinline__ void search_ws_item(const SearchArgs &a, int item)
 {
     constexpr int h = S / 2;
     constexpr int NWAVE = WS_NWAVE, NT = 64 * NWAVE;
@@ -208,9 +208,6 @@ __global__ __launch_bounds__(64 * WS_NWAVE) __attribute__((amdgpu_waves_per_eu(4
     __shared__ __align__(16) float win[XCH ? 1 : 2][WY * LS];
     __shared__ __align__(16) float xch[XCH ? NXR * 128 : 2];
 
-    const int item = xcd_item(blockIdx.x, gridDim.x);
-    if (item >= a.n_items)
-        return;
     // work order: blocks of `tblock` velocity-sorted trajectories; within a
     // block the trajectory index runs fastest, then the tile
     const int ntiles = a.ntx * a.nty;
@@ -577,20 +574,47 @@ __global__ __launch_bounds__(64 * WS_NWAVE) __attribute__((amdgpu_waves_per_eu(4
     }
 }
 
+// One request: block b takes work item xcd_item(b) of the request.
+template <int S, bool SEP, int SRC, int RPL>
+__global__ __launch_bounds__(64 * WS_NWAVE) __attribute__((amdgpu_waves_per_eu(4))) void k_search_ws(SearchArgs a)
+{
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item < a.n_items)
+        search_ws_item<S, SEP, SRC, RPL>(a, item);
+}
+
+// A step of the serving loop: block ranges for the work items of several requests.
+template <int S, bool SEP, int SRC, int RPL>
+__global__ __launch_bounds__(64 * WS_NWAVE) __attribute__((amdgpu_waves_per_eu(4))) void k_search_ws_step(StepArgs s)
+{
+    int r, item;
+    if (step_item(s, r, item))
+        search_ws_item<S, SEP, SRC, RPL>(step_args(s, r), item);
+}
+
 namespace {
 
-template <int S, bool SEP, int RPL>
-hipError_t launch_ws_src(hipStream_t st, const SearchArgs &a)
+template <int S, bool SEP, int SRC, int RPL>
+void launch_ws_kernel(hipStream_t st, const SearchArgs &a, const StepArgs *step, int nblocks)
 {
-    const dim3 grid(xcd_grid(a.n_items)), block(64 * WS_NWAVE);
+    const dim3 block(64 * WS_NWAVE);
+    if (step)
+        hipLaunchKernelGGL((k_search_ws_step<S, SEP, SRC, RPL>), dim3(nblocks), block, 0, st, *step);
+    else
+        hipLaunchKernelGGL((k_search_ws<S, SEP, SRC, RPL>), dim3(xcd_grid(a.n_items)), block, 0, st, a);
+}
+
+template <int S, bool SEP, int RPL>
+hipError_t launch_ws_src(hipStream_t st, const SearchArgs &a, const StepArgs *step, int nblocks)
+{
     if (a.Z4) {
-        hipLaunchKernelGGL((k_search_ws<S, SEP, SRC_Z, RPL>), grid, block, 0, st, a);
+        launch_ws_kernel<S, SEP, SRC_Z, RPL>(st, a, step, nblocks);
     } else {
         switch (a.dtype) {
-        case TNO_F32: hipLaunchKernelGGL((k_search_ws<S, SEP, TNO_F32, RPL>), grid, block, 0, st, a); break;
-        case TNO_BF16: hipLaunchKernelGGL((k_search_ws<S, SEP, TNO_BF16, RPL>), grid, block, 0, st, a); break;
-        case TNO_F16: hipLaunchKernelGGL((k_search_ws<S, SEP, TNO_F16, RPL>), grid, block, 0, st, a); break;
-        case TNO_FP8_E4M3: hipLaunchKernelGGL((k_search_ws<S, SEP, TNO_FP8_E4M3, RPL>), grid, block, 0, st, a); break;
+        case TNO_F32: launch_ws_kernel<S, SEP, TNO_F32, RPL>(st, a, step, nblocks); break;
+        case TNO_BF16: launch_ws_kernel<S, SEP, TNO_BF16, RPL>(st, a, step, nblocks); break;
+        case TNO_F16: launch_ws_kernel<S, SEP, TNO_F16, RPL>(st, a, step, nblocks); break;
+        case TNO_FP8_E4M3: launch_ws_kernel<S, SEP, TNO_FP8_E4M3, RPL>(st, a, step, nblocks); break;
         default: return hipErrorInvalidValue;
         }
     }
@@ -598,29 +622,30 @@ hipError_t launch_ws_src(hipStream_t st, const SearchArgs &a)
 }
 
 template <int RPL>
-hipError_t launch_ws_rpl(hipStream_t st, int S, bool sep, const SearchArgs &a)
+hipError_t launch_ws_rpl(hipStream_t st, int S, bool sep, const SearchArgs &a, const StepArgs *step, int nblocks)
 {
     switch (S * 2 + (sep ? 1 : 0)) {
-    case 3: return launch_ws_src<1, true, RPL>(st, a);
-    case 2: return launch_ws_src<1, false, RPL>(st, a);
-    case 7: return launch_ws_src<3, true, RPL>(st, a);
-    case 6: return launch_ws_src<3, false, RPL>(st, a);
-    case 11: return launch_ws_src<5, true, RPL>(st, a);
-    case 10: return launch_ws_src<5, false, RPL>(st, a);
+    case 3: return launch_ws_src<1, true, RPL>(st, a, step, nblocks);
+    case 2: return launch_ws_src<1, false, RPL>(st, a, step, nblocks);
+    case 7: return launch_ws_src<3, true, RPL>(st, a, step, nblocks);
+    case 6: return launch_ws_src<3, false, RPL>(st, a, step, nblocks);
+    case 11: return launch_ws_src<5, true, RPL>(st, a, step, nblocks);
+    case 10: return launch_ws_src<5, false, RPL>(st, a, step, nblocks);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_search_ws(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a)
+hipError_t launch_search_ws(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a,
+                            const StepArgs *step, int nblocks)
 {
     if (!a.Z4 && (a.W % 4 != 0 || !a.R || !a.ivar32 || (a.dtype != TNO_F32 && !a.scales)))
         return hipErrorInvalidValue;
     if (variant == SEARCH_WS)
-        return launch_ws_rpl<8>(st, S, sep, a);
+        return launch_ws_rpl<8>(st, S, sep, a, step, nblocks);
     if (variant == SEARCH_WS4)
-        return launch_ws_rpl<4>(st, S, sep, a);
+        return launch_ws_rpl<4>(st, S, sep, a, step, nblocks);
     return hipErrorInvalidValue;
 }
 

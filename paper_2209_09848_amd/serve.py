@@ -117,8 +117,12 @@ class StackPool:
 
 
 def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=16,
-               max_inflight=8, log=None, graphs=False):
-    """Serve `specs` in arrival order.  Returns per-request records."""
+               max_inflight=8, log=None, mode="eager", keep=False, stats=None):
+    """Serve `specs` in arrival order; mode "eager" (each request's kernels on
+    a pool stream), "graphs" (each request as a HIP graph) or "batch" (the
+    searches of admitted requests share steps).  Returns per-request records
+    (keep=True: with each request's outputs and stack key, for checks); a
+    `stats` dict receives the handle's statistics at the end."""
     import torch
     pool = StackPool({s.key: (s.side, s.frames) for s in specs}, dtype, device)
     vel_all = torch.from_numpy(bank).to(device)
@@ -129,7 +133,7 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
     pending = collections.deque(sorted(specs, key=lambda s: s.arrival))
     inflight = {}
     h = tno.Search(0, own_streams=True, max_inflight=max_inflight,
-                   hbm_budget_bytes=int(budget_gb * 1e9), graphs=graphs)
+                   hbm_budget_bytes=int(budget_gb * 1e9), graphs=mode == "graphs", batch=mode == "batch")
     t0 = time.perf_counter()
     try:
         while pending or queue or inflight:
@@ -172,11 +176,18 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
                     raise tno.TnoError(rc, res.message.decode(errors="replace"))
                 s = inflight[ticket][0]
                 t_done = time.perf_counter() - t0
-                recs.append({"key": s.key, "side": s.side, "frames": s.frames,
-                             "traj": int(len(s.traj_idx)), "arrival": s.arrival, "done": t_done,
-                             "latency_ms": (t_done - s.arrival) * 1e3, "device_ms": res.device_ms,
-                             "updates": int(res.updates),
-                             "topk": tno.decode_candidates(inflight[ticket][1]["topk"], res.n_topk)})
+                rec = {"key": s.key, "side": s.side, "frames": s.frames,
+                       "traj": int(len(s.traj_idx)), "arrival": s.arrival, "done": t_done,
+                       "latency_ms": (t_done - s.arrival) * 1e3, "device_ms": res.device_ms,
+                       "updates": int(res.updates),
+                       "topk": tno.decode_candidates(inflight[ticket][1]["topk"], res.n_topk)}
+                if keep:
+                    o = inflight[ticket][1]
+                    rec["spec"] = s
+                    rec["traj_max"] = o["traj_max"].cpu().numpy()
+                    rec["best_snr"] = o["best_snr"].cpu().numpy()
+                    rec["best_traj"] = o["best_traj"].cpu().numpy()
+                recs.append(rec)
                 done.append(ticket)
                 if log:
                     log("done key %d %dx%dx%d J=%d latency %.1f ms" %
@@ -185,6 +196,9 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
                 del inflight[t]
             if not done:
                 time.sleep(0.0005)
+        if stats is not None:
+            st = tno.tno_search_stats(h.h)
+            stats.update({f: getattr(st, f) for f, _ in st._fields_ if f != "reserved"})
     finally:
         h.close()
     return recs
@@ -209,8 +223,8 @@ def main(argv=None):
     ap.add_argument("--max-side", type=int, default=2048)
     ap.add_argument("--dtypes", default="f32,bf16")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--modes", default="eager,graphs",
-                    help="eager launches and/or requests run as HIP graphs")
+    ap.add_argument("--modes", default="eager,batch",
+                    help="eager launches, requests run as HIP graphs, and/or batched steps")
     args = ap.parse_args(argv)
 
     def log(m):
@@ -232,10 +246,9 @@ def main(argv=None):
         for mode in args.modes.split(","):
             sp = poisson_arrivals([Spec(s.key, s.side, s.frames, s.traj_idx) for s in specs], rate,
                                   args.seed)
-            name = dt if mode == "eager" else dt + "+graphs"
+            name = dt if mode == "eager" else dt + "+" + mode
             log("serving %d requests, %s" % (len(sp), name))
-            recs = run_stream(sp, bank, dtype=dt, budget_gb=args.budget_gb, log=None,
-                              graphs=mode == "graphs")
+            recs = run_stream(sp, bank, dtype=dt, budget_gb=args.budget_gb, log=None, mode=mode)
             out["forms"][name] = summarize(recs, args.warm)
             log("%s: %s" % (name, json.dumps(out["forms"][name])))
     print(json.dumps(out), flush=True)

@@ -30,6 +30,7 @@ TNO_PRF_GAUSS_SAMPLED, TNO_PRF_GAUSS_INTEGRATED, TNO_PRF_TABLE = 0, 1, 2
 TNO_MAX_TABLE_Q = 64
 TNO_CFG_GRAPHS = 1
 TNO_CFG_AUTOTUNE = 2
+TNO_CFG_BATCH = 4
 SEARCH_VARIANTS = ("w4c2", "w8c2", "w2c2", "w4c1", "w8c1", "w4c4", "w2c2r16", "w4c2r16", "ws", "ws4")
 TNO_REQ_DEVICE_PTRS = 1
 TNO_REQ_VALIDATE = 2
@@ -118,7 +119,9 @@ class tno_stats(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("in_use_bytes", ctypes.c_uint64),
                 ("held_bytes", ctypes.c_uint64), ("cached_bytes", ctypes.c_uint64),
                 ("device_allocs", ctypes.c_uint64), ("inflight", ctypes.c_int32),
-                ("resident_stacks", ctypes.c_int32), ("reserved", ctypes.c_uint64 * 4)]
+                ("resident_stacks", ctypes.c_int32), ("batch_steps", ctypes.c_uint64),
+                ("batch_items", ctypes.c_uint64), ("batch_shared", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint64 * 1)]
 
 
 EXPORTS = ("tno_search_create", "tno_search_submit", "tno_search_poll", "tno_search_destroy",
@@ -283,12 +286,14 @@ class Search:
 
     def __init__(self, device: int = 0, max_inflight: int = 64, hbm_budget_bytes: int = 0,
                  stream=None, own_streams: bool = False, autotune: bool = False,
-                 tune_cache_path: str | None = None, graphs: bool = False):
+                 tune_cache_path: str | None = None, graphs: bool = False, batch: bool = False):
         """own_streams=True: the library runs requests on its own pool of streams
         (concurrent requests overlap; inputs must be complete before submit);
-        otherwise every request runs on `stream` (default: torch's current)."""
+        otherwise every request runs on `stream` (default: torch's current).
+        batch=True (implies own_streams): continuous batching of the searches
+        of admitted requests into shared steps."""
         import torch
-        if own_streams:
+        if own_streams or batch:
             stream = 0
         elif stream is None:
             stream = torch.cuda.current_stream(device).cuda_stream
@@ -296,7 +301,8 @@ class Search:
         cfg.device = device
         cfg.max_inflight = max_inflight
         cfg.hbm_budget_bytes = hbm_budget_bytes
-        cfg.flags = (TNO_CFG_AUTOTUNE if autotune else 0) | (TNO_CFG_GRAPHS if graphs else 0)
+        cfg.flags = ((TNO_CFG_AUTOTUNE if autotune else 0) | (TNO_CFG_GRAPHS if graphs else 0) |
+                     (TNO_CFG_BATCH if batch else 0))
         cfg.reserved = 0
         cfg.stream = ctypes.c_void_p(stream) if stream else None
         self._path = tune_cache_path.encode() if tune_cache_path else None

@@ -26,6 +26,10 @@ hipError_t launch_trail(hipStream_t, int, int, int, bool, const int32_t *, const
                         int2 *, double *, int32_t *) { return hipErrorNotSupported; }
 hipError_t launch_lambda(hipStream_t, const LambdaArgs &) { return hipErrorNotSupported; }
 hipError_t launch_search(hipStream_t, int, bool, int, const SearchArgs &) { return hipErrorNotSupported; }
+hipError_t launch_search_step(hipStream_t, int, bool, int, const SearchArgs &, const StepArgs &, int)
+{
+    return hipErrorNotSupported;
+}
 hipError_t launch_trajmax(hipStream_t, int, int, int, int, const uint64_t *, const float *, const float *,
                           void *) { return hipErrorNotSupported; }
 hipError_t launch_best(hipStream_t, int, int, const float *, float *, int32_t *) { return hipErrorNotSupported; }
