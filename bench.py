@@ -340,8 +340,108 @@ def side_measurements(h_args, R, sig_t, times_t, vel_t, t_ref, k, out, dev, U):
         "sigma0": ro.sigma0, "n_clipped": int(ro.n_clipped), "n_masked": int(ro.n_masked)}
     log("background re-fit: %.1f ms (%.2f TB/s)" % (m, nbytes / (m * 1e-3) / 1e12))
     del p
+    res["precision_forms"] = precision_forms(R, sig_t, times_t, vel_t, t_ref, k, out, dev, U)
     res["batched_shells"] = batched_form(dev)
+    res["serving"] = serving_form()
     return res
+
+
+def footprint_bytes(H, W, T, times, vel, dtype, stage=False, k=100, stamp=5):
+    """tno_search_footprint of a request over a stack resident under a key
+    (its codes, tile scales and sigma counted once) with the top-k and no
+    caller maps: the device bytes the request holds while in flight."""
+    import ctypes
+
+    import numpy as np
+
+    from paper_2209_09848_amd import tno
+    times = np.ascontiguousarray(times, np.float64)
+    vel = np.ascontiguousarray(vel, np.float64)
+    req = tno.tno_request()
+    req.height, req.width, req.n_frames, req.dtype = H, W, T, tno.DTYPE_CODE[dtype]
+    req.times = times.ctypes.data_as(ctypes.c_void_p)
+    req.velocities = vel.ctypes.data_as(ctypes.c_void_p)
+    req.t_ref = float("nan")
+    req.prf = tno.tno_prf(0, stamp, 0.7, None, 0, 0)
+    req.n_traj = vel.shape[0]
+    req.top_k = k
+    req.stack_key = 1
+    req.flags = tno.TNO_REQ_STAGE_FP32 if stage else 0
+    req.reserved = 0
+    topk = np.zeros((k, 5), np.int32)
+    out = tno.tno_outputs()
+    out.topk = topk.ctypes.data_as(ctypes.c_void_p)
+    return int(tno.tno_search_footprint(req, out))
+
+
+def precision_forms(R, sig_t, times_t, vel_t, t_ref, k, out, dev, U):
+    """The FFI request with its stack stored as BF16, FP16 and FP8-e4m3
+    (per-64x64-tile scales): searched in place (default) and, for BF16, from
+    a staged FP32 copy; one warm-up and two measured requests each."""
+    import numpy as np
+    import torch
+
+    from paper_2209_09848_amd import tno
+    T, H, W = (int(v) for v in R.shape)
+    times = times_t.cpu().numpy()
+    vel = vel_t.cpu().numpy()
+    res = {"f32": {"footprint_bytes": footprint_bytes(H, W, T, times, vel, "f32")}}
+    for dtype, stage in (("bf16", False), ("bf16", True), ("f16", False), ("fp8_e4m3", False)):
+        codes = torch.empty((T, H, W), device=dev, dtype=torch.uint8 if dtype == "fp8_e4m3" else torch.int16)
+        scales = torch.empty((T, (H + 63) // 64, (W + 63) // 64), device=dev)
+        assert tno.tno_quantize(T, H, W, tno.DTYPE_CODE[dtype], R.data_ptr(), codes.data_ptr(),
+                                scales.data_ptr(), None) == 0
+        torch.cuda.synchronize()
+        flags = tno.TNO_REQ_DEVICE_PTRS | (tno.TNO_REQ_STAGE_FP32 if stage else 0)
+        req = tno.make_request(codes, sig_t, times_t, vel_t, t_ref=t_ref, top_k=k, dtype=dtype,
+                               scales=scales, flags=flags)
+        with tno.Search(0) as h:
+            runs = [h.wait(h.submit(req, out)) for _ in range(3)][1:]
+        name = dtype + ("_staged_fp32" if stage else "_in_place")
+        sm = float(np.mean([r.search_ms for r in runs]))
+        dm = float(np.mean([r.device_ms for r in runs]))
+        res[name] = {"search_ms": sm, "device_ms": dm, "updates_per_s": U / (dm * 1e-3),
+                     "stack_bytes": T * H * W * codes.element_size() + scales.numel() * 4,
+                     "footprint_bytes": footprint_bytes(H, W, T, times, vel, dtype, stage=stage)}
+        log("precision form %s: search %.1f ms, device %.1f ms, footprint %.2f GB"
+            % (name, sm, dm, res[name]["footprint_bytes"] / 1e9))
+        del codes, scales
+        torch.cuda.empty_cache()
+    return res
+
+
+def serving_form(n_requests=48, warm=8, load=0.7, max_side=1024, seed=0):
+    """A Poisson stream of uneven requests (cutouts 256..max_side px, 200-1000
+    frames, 16-256 trajectories of the shell bank; stacks resident under keys,
+    about half the requests reusing one) at `load` times the back-to-back
+    capacity of the plain FP32 search on a sample of the mix; FP32, BF16 read
+    in place and BF16 staged into FP32 per request, each with eager
+    per-request launches and with continuous batching, at the same arrival
+    rate."""
+    import numpy as np
+
+    from paper_2209_09848_amd import serve, synth
+    bank, _ = synth.grid_shells()
+    sides = list(range(256, max_side + 1, 256))
+    shapes = serve.draw_stack_shapes(8, seed, sides=sides)
+    specs = serve.draw_requests(n_requests + warm, shapes, bank.shape[0], seed)
+    cal = [serve.Spec(s.key, s.side, s.frames, s.traj_idx, 0.0) for s in specs[:8]]
+    crec = serve.run_stream(cal, bank, dtype="f32", max_inflight=1)
+    mean_s = float(np.mean([x["device_ms"] for x in crec])) * 1e-3
+    rate = load / mean_s
+    out = {"workload": "%d requests (+%d warm-up), cutouts 256-%d px, 200-1000 frames, 16-256 trajectories"
+                       % (n_requests, warm, max_side), "load": load, "arrival_rate_per_s": rate, "forms": {}}
+    for dtype, stage in (("f32", False), ("bf16", False), ("bf16", True)):
+        for mode in ("eager", "batch"):
+            sp = serve.poisson_arrivals([serve.Spec(s.key, s.side, s.frames, s.traj_idx) for s in specs],
+                                        rate, seed)
+            recs = serve.run_stream(sp, bank, dtype=dtype, mode=mode, stage_fp32=stage)
+            name = dtype + ("_staged" if stage else "") + "_" + mode
+            out["forms"][name] = serve.summarize(recs, warm)
+            log("serving %s: p50 %.1f ms, p99 %.1f ms, %.3g updates/s"
+                % (name, out["forms"][name]["p50_ms"], out["forms"][name]["p99_ms"],
+                   out["forms"][name]["updates_per_s"]))
+    return out
 
 
 def batched_form(dev, autotune=True):
@@ -372,22 +472,32 @@ def batched_form(dev, autotune=True):
     req = tno.make_request(codes, torch.from_numpy(sigma).to(dev), torch.from_numpy(times).to(dev),
                            torch.from_numpy(vel).to(dev), t_ref=t_ref, top_k=100, dtype="bf16",
                            scales=scales)
-    with tempfile.TemporaryDirectory() as d:
-        path = d + "/tune.txt"
-        with tno.Search(0, autotune=autotune, tune_cache_path=path) as h:
-            first = h.wait(h.submit(req, out))
-            runs = [h.wait(h.submit(req, out)) for _ in range(2)]
-        tuned = ([l for l in open(path).read().splitlines() if not l.startswith("#")]
-                 if os.path.exists(path) else [])
-    dm = float(np.mean([r.device_ms for r in runs]))
-    sm = float(np.mean([r.search_ms for r in runs]))
     U = J * H * W * T
-    log("batched form: %.1f ms per request (search %.1f ms), tuning request %.1f ms, tuned %s"
-        % (dm, sm, first.device_ms, tuned))
-    return {"workload": "batched_1024x1024x1000_bf16_j2048_8shells", "device_ms": dm, "search_ms": sm,
-            "updates_per_s": U / (dm * 1e-3), "search_frac_nonpacked": 20 * U / (sm * 1e-3) / 1e12 / PEAK_FP32_NONPACKED,
-            "first_request_ms_with_autotune" if autotune else "first_request_ms": first.device_ms,
-            "tuned": tuned[0].split()[2:4] if tuned else None}
+    res = {"workload": "batched_1024x1024x1000_bf16_j2048_8shells"}
+    for stage in (True, False):
+        r = req
+        if stage:
+            r = tno.make_request(codes, torch.from_numpy(sigma).to(dev), torch.from_numpy(times).to(dev),
+                                 torch.from_numpy(vel).to(dev), t_ref=t_ref, top_k=100, dtype="bf16",
+                                 scales=scales, flags=tno.TNO_REQ_DEVICE_PTRS | tno.TNO_REQ_STAGE_FP32)
+        with tempfile.TemporaryDirectory() as d:
+            path = d + "/tune.txt"
+            with tno.Search(0, autotune=autotune, tune_cache_path=path) as h:
+                first = h.wait(h.submit(r, out))
+                runs = [h.wait(h.submit(r, out)) for _ in range(2)]
+            tuned = ([l for l in open(path).read().splitlines() if not l.startswith("#")]
+                     if os.path.exists(path) else [])
+        dm = float(np.mean([x.device_ms for x in runs]))
+        sm = float(np.mean([x.search_ms for x in runs]))
+        name = "staged_fp32" if stage else "in_place"
+        log("batched form (%s): %.1f ms per request (search %.1f ms), tuning request %.1f ms, tuned %s"
+            % (name, dm, sm, first.device_ms, tuned))
+        res[name] = {"device_ms": dm, "search_ms": sm, "updates_per_s": U / (dm * 1e-3),
+                     "search_TFLOPs": 20 * U / (sm * 1e-3) / 1e12,
+                     "first_request_ms_with_autotune" if autotune else "first_request_ms": first.device_ms,
+                     "tuned": tuned[0].split()[2:4] if tuned else None,
+                     "footprint_bytes": footprint_bytes(H, W, T, times, vel, "bf16", stage=stage)}
+    return res
 
 
 if __name__ == "__main__":

@@ -116,6 +116,15 @@ typedef struct {
     void *stream;                /* hipStream_t to run on, or NULL for an own stream */
     const char *tune_cache_path; /* text tuning cache read at create and rewritten after each
                                     tuning (one line per arch and shape class), or NULL */
+    uint64_t slab_bytes;         /* device bytes of one trajectory slab (0: 2 GiB).  A request
+                                    searches its trajectories in slabs, consecutive runs of its
+                                    velocity-sorted search order: the FP64 normaliser (8 bytes
+                                    per start pixel and trajectory) and the slab's SNR and flux
+                                    maps (4 bytes each) exist for one slab at a time; the bank
+                                    maximum, per-trajectory peaks and top-k are merged slab
+                                    after slab, and maps the caller asked for receive each
+                                    slab's rows.  A slab holds at least one trajectory.
+                                    Results do not depend on it. */
 } tno_config;
 
 /* Stamp weights of frame k (Sec. 3.2): with phase (f_y, f_x) in [-1/2, 1/2)
@@ -195,8 +204,9 @@ typedef struct {
  * according to TNO_REQ_DEVICE_PTRS.  Caller-owned; written only between a
  * successful submit and the ticket's terminal poll. */
 typedef struct {
-    float *snr;                  /* [J][H][W] */
-    float *flux;                 /* [J][H][W] */
+    float *snr;                  /* [J][H][W]; NULL: never held whole on the device (each
+                                    trajectory slab's rows only, see slab_bytes) */
+    float *flux;                 /* [J][H][W]; NULL: likewise */
     float *best_snr;             /* [H][W] max over the bank, ties to the lowest j */
     int32_t *best_traj;          /* [H][W] arg-max j */
     tno_peak *traj_max;          /* [J] per-trajectory max, ties to the smallest y*W+x */

@@ -86,11 +86,14 @@ struct SearchArgs {
     const float *ivar32;     // direct source: ivar [H][W]
     int dtype, nqy, nqx;
     const int32_t *tab32;    // [J][T][table_stride(S, sep)]
+    // One launch searches a slab of J trajectories; its maps hold one row of
+    // H*W values per trajectory of the slab, trajectory j in row jrow[j].
     const double *lam;       // [J][H][W]
     float *snr;              // [J][H][W]
     float *flux;             // [J][H][W]
-    uint64_t *tile_keys;     // [J][ntiles]
-    const int32_t *perm;     // [J] search order of the trajectories (velocity-sorted)
+    uint64_t *tile_keys;     // [all trajectories][ntiles], by trajectory number
+    const int32_t *perm;     // [J] the slab's trajectories in search order (velocity-sorted)
+    const int32_t *jrow;     // [all trajectories] row of each in its slab's maps
     int H, W, T, J;
     int Hp, Wp4, Pt, Pl;
     int ntx, nty, n_items;
@@ -122,7 +125,8 @@ struct LambdaArgs {
     const int2 *colmeta;     // per major line: (minor offset of run start, run length)
     const double *kvals;
     const double *ivar64;    // [Hq][Wq] in the launch's frame: ivar at (Pyt + y, Pxl + x), zero around it
-    double *lam;             // [J][H0][W0]
+    double *lam;             // [slab][H0][W0]: trajectory j in row jrow[j]
+    const int32_t *jrow;
     const int32_t *jlist;    // [nj] trajectories of this launch
     int H, W;                // image in the launch's frame (W0, H0 when transposed)
     int H0, W0;              // image
@@ -170,18 +174,28 @@ hipError_t launch_search_step(hipStream_t st, int S, bool sep, int variant, cons
 // with `step`, the serving loop's multi-request launch.
 hipError_t launch_search_ws(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a,
                             const StepArgs *step = nullptr, int nblocks = 0);
-hipError_t launch_trajmax(hipStream_t st, int J, int ntiles, int W, int HW,
+// Slab reductions: a slab's maps have J rows, row r holding trajectory
+// rows[r] (increasing with r).
+// Peaks of the slab's trajectories: traj_max_out[rows[r]] from row r.
+hipError_t launch_trajmax(hipStream_t st, int J, int ntiles, int W, int HW, const int32_t *rows,
                           const uint64_t *tile_keys, const float *snr, const float *flux,
                           void *traj_max_out);
-hipError_t launch_best(hipStream_t st, int J, int HW, const float *snr, float *best_snr,
-                       int32_t *best_traj);
-hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int64_t N, int HW,
-                       int W, int k, TopkState *state, uint32_t *chunk_cnt, int64_t n_chunks,
-                       uint64_t *cand, void *topk_out);
+// The bank maximum merged with one slab; first: the slab starts it.
+hipError_t launch_best(hipStream_t st, int J, int64_t HW, const int32_t *rows, bool first, const float *snr,
+                       const float *flux, float *best_snr, int32_t *best_traj, float *best_flux);
+// The exact top k of one slab's N = J*HW scores merged into the k_run
+// candidates kept in topk_out from earlier slabs (0: none).
+hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int64_t N, int64_t HW,
+                       int W, const int32_t *rows, int k, int k_run, TopkState *state, uint32_t *chunk_cnt,
+                       int64_t n_chunks, uint64_t *cand, void *topk_out);
+// Row r of a slab's map (J rows of HW values) into row rows[r] of a map with
+// a row per trajectory.
+hipError_t launch_rows_out(hipStream_t st, int J, int64_t HW, const int32_t *rows, const float *slab_map,
+                           float *full_map);
 // Doubles in each of the two block-sum buffers of the significance pass.
 int64_t significance_block_values(int H, int W);
 hipError_t launch_significance(hipStream_t st, int H, int W, int box, float thr, int k,
-                               const float *best_snr, const int32_t *best_traj, const float *flux,
+                               const float *best_snr, const int32_t *best_traj, const float *best_flux,
                                double *r1, double *r2, double *b1, double *b2, float *sig,
                                TopkState *state, uint32_t *chunk_cnt, int64_t n_chunks,
                                uint64_t *cand, tno_detection *det, int32_t *counts);

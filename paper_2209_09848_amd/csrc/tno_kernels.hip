@@ -487,13 +487,14 @@ __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
             }
         }
     }
+    const int jr = a.jrow[j];   // the trajectory's row of the slab's map
     if (x < a.W) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             int y = y0 + r;
             if (y < a.H) {
                 // (y, x) of the launch's frame; transposed: image row x, column y
-                const size_t o = a.tr ? ((size_t)j * a.H0 + x) * a.W0 + y : ((size_t)j * a.H0 + y) * a.W0 + x;
+                const size_t o = a.tr ? ((size_t)jr * a.H0 + x) * a.W0 + y : ((size_t)jr * a.H0 + y) * a.W0 + x;
                 a.lam[o] = acc[r];
             }
         }
@@ -902,7 +903,9 @@ __device__ __forceinline__ void search_item(const SearchArgs &a, int item)
             }
     }
 
-    // epilogue: SNR and flux, and the tile's largest (SNR, -pixel) key
+    // epilogue: SNR and flux (into the trajectory's row of the slab's
+    // maps), and the tile's largest (SNR, -pixel) key
+    const int jr = a.jrow[j];
     uint64_t best = 0;
     const size_t HW = (size_t)a.H * a.W;
 #pragma unroll
@@ -914,7 +917,7 @@ __device__ __forceinline__ void search_item(const SearchArgs &a, int item)
             if (y < a.H && x < a.W) {
                 const double nu = acc[o][c] + (double)part[o][c];
                 const size_t p = (size_t)y * a.W + x;
-                const size_t mp = (size_t)j * HW + p;
+                const size_t mp = (size_t)jr * HW + p;
                 const double L = a.lam[mp];
                 float snr = 0.0f, flux = 0.0f;
                 if (L > 0.0) {
@@ -1053,13 +1056,15 @@ hipError_t launch_search_step(hipStream_t st, int S, bool sep, int variant, cons
 
 // ------------------------------------------------------------------ reductions
 
-// Per trajectory: the largest tile key; ties in SNR go to the smallest pixel
-// index because the key stores 0xFFFFFFFF - (y*W + x) in its low half.
-__global__ void k_trajmax(int ntiles, int W, int HW, const uint64_t *__restrict__ tile_keys,
-                          const float *__restrict__ snr, const float *__restrict__ flux,
-                          tno_peak *__restrict__ out)
+// Per trajectory of a slab (block r: trajectory rows[r], row r of the slab's
+// maps): the largest tile key; ties in SNR go to the smallest pixel index
+// because the key stores 0xFFFFFFFF - (y*W + x) in its low half.
+__global__ void k_trajmax(int ntiles, int W, int HW, const int32_t *__restrict__ rows,
+                          const uint64_t *__restrict__ tile_keys, const float *__restrict__ snr,
+                          const float *__restrict__ flux, tno_peak *__restrict__ out)
 {
-    const int j = blockIdx.x;
+    const int r = blockIdx.x;
+    const int j = rows[r];
     uint64_t m = 0;
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
         uint64_t v = tile_keys[(size_t)j * ntiles + t];
@@ -1078,7 +1083,7 @@ __global__ void k_trajmax(int ntiles, int W, int HW, const uint64_t *__restrict_
             m = wm[w] > m ? wm[w] : m;
         m = wm[0] > m ? wm[0] : m;
         uint32_t p = 0xFFFFFFFFu - (uint32_t)(m & 0xFFFFFFFFu);
-        size_t mp = (size_t)j * HW + p;
+        size_t mp = (size_t)r * HW + p;
         tno_peak pk;
         pk.snr = snr[mp];
         pk.flux = flux[mp];
@@ -1088,40 +1093,85 @@ __global__ void k_trajmax(int ntiles, int W, int HW, const uint64_t *__restrict_
     }
 }
 
-hipError_t launch_trajmax(hipStream_t st, int J, int ntiles, int W, int HW,
+hipError_t launch_trajmax(hipStream_t st, int J, int ntiles, int W, int HW, const int32_t *rows,
                           const uint64_t *tile_keys, const float *snr, const float *flux,
                           void *traj_max_out)
 {
-    hipLaunchKernelGGL(k_trajmax, dim3(J), dim3(256), 0, st, ntiles, W, HW, tile_keys, snr, flux,
+    hipLaunchKernelGGL(k_trajmax, dim3(J), dim3(256), 0, st, ntiles, W, HW, rows, tile_keys, snr, flux,
                        (tno_peak *)traj_max_out);
     return hipGetLastError();
 }
 
-// Per start pixel: the bank maximum (Sec. 3.2); strict '>' keeps the lowest j.
-__global__ void k_best(int J, int HW, const float *__restrict__ snr, float *__restrict__ best_snr,
-                       int32_t *__restrict__ best_traj)
+// Per start pixel: the bank maximum (Sec. 3.2) over the trajectories searched
+// so far, merged with one more slab (row r of `snr` and `flux` holds
+// trajectory rows[r]); among equal scores the lowest trajectory number wins.
+// best_flux is the flux of the maximising trajectory.  first: the slab
+// starts the maximum.
+__global__ void k_best(int J, int64_t HW, const int32_t *__restrict__ rows, int first,
+                       const float *__restrict__ snr, const float *__restrict__ flux,
+                       float *__restrict__ best_snr, int32_t *__restrict__ best_traj,
+                       float *__restrict__ best_flux)
 {
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += gridDim.x * blockDim.x) {
-        float b = snr[p];
-        int bj = 0;
-        for (int j = 1; j < J; ++j) {
-            float s = snr[(size_t)j * HW + p];
-            if (s > b) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < HW;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        float b;
+        int bj, m0;
+        int64_t bm;   // slab row of the maximum, or -1: kept from earlier slabs
+        if (first) {
+            b = snr[p];
+            bj = rows[0];
+            bm = 0;
+            m0 = 1;
+        } else {
+            b = best_snr[p];
+            bj = best_traj[p];
+            bm = -1;
+            m0 = 0;
+        }
+        for (int m = m0; m < J; ++m) {
+            const float s = snr[(int64_t)m * HW + p];
+            const int j = rows[m];
+            if (s > b || (s == b && j < bj)) {
                 b = s;
                 bj = j;
+                bm = m;
             }
         }
-        best_snr[p] = b;
-        best_traj[p] = bj;
+        if (bm >= 0) {
+            best_snr[p] = b;
+            best_traj[p] = bj;
+            best_flux[p] = flux[bm * HW + p];
+        }
     }
 }
 
-hipError_t launch_best(hipStream_t st, int J, int HW, const float *snr, float *best_snr,
-                       int32_t *best_traj)
+hipError_t launch_best(hipStream_t st, int J, int64_t HW, const int32_t *rows, bool first, const float *snr,
+                       const float *flux, float *best_snr, int32_t *best_traj, float *best_flux)
 {
-    int blocks = (HW + 255) / 256;
+    int64_t blocks = (HW + 255) / 256;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_best, dim3(blocks), dim3(256), 0, st, J, HW, snr, best_snr, best_traj);
+    hipLaunchKernelGGL(k_best, dim3((unsigned)blocks), dim3(256), 0, st, J, HW, rows, (int)first, snr, flux,
+                       best_snr, best_traj, best_flux);
+    return hipGetLastError();
+}
+
+// Row r of a slab's map into row rows[r] of the map with a row per trajectory.
+__global__ void k_rows_out(int64_t HW, const int32_t *__restrict__ rows, const float *__restrict__ src,
+                           float *__restrict__ dst)
+{
+    const int r = blockIdx.y;
+    const float *s = src + (int64_t)r * HW;
+    float *d = dst + (int64_t)rows[r] * HW;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < HW; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = s[i];
+}
+
+hipError_t launch_rows_out(hipStream_t st, int J, int64_t HW, const int32_t *rows, const float *slab_map,
+                           float *full_map)
+{
+    const int64_t bx = std::min<int64_t>((HW + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_rows_out, dim3((unsigned)bx, (unsigned)J), dim3(256), 0, st, HW, rows, slab_map,
+                       full_map);
     return hipGetLastError();
 }
 
@@ -1310,25 +1360,69 @@ __device__ void sort_candidates(uint64_t *sk, uint64_t *si, const uint64_t *cand
     }
 }
 
-// Sort the k candidates and write them as (snr, flux, traj, y, x).
-__global__ __launch_bounds__(1024) void k_topk_final(const float *__restrict__ flux, int64_t N,
-                                                     int k, int HW, int W,
+// Merge the k_new candidates of one slab (unsorted (key, index into the
+// slab's map) pairs in cand, row r of the map holding trajectory rows[r];
+// flux from the slab's map) into the k_run
+// candidates kept from earlier slabs (sorted, in out) and write back the first
+// k_out of the union in the top-k order as (snr, flux, traj, y, x).  The
+// order is total (SNR descending, then flat index j*H*W + y*W + x ascending),
+// so the top k of all slabs is the top k of the slabs' top k.
+constexpr int MERGE_N = 2 * TNO_MAX_TOPK;
+__global__ __launch_bounds__(1024) void k_topk_merge(int k_new, int k_run, int k_out, int64_t N, int64_t HW,
+                                                     int W, const int32_t *__restrict__ rows,
                                                      const uint64_t *__restrict__ cand,
+                                                     const float *__restrict__ flux,
                                                      tno_candidate *__restrict__ out)
 {
-    __shared__ uint64_t sk[TNO_MAX_TOPK];
-    __shared__ uint64_t si[TNO_MAX_TOPK];
-    const int t = threadIdx.x;
-    sort_candidates(sk, si, cand, k);
-    if (t < k) {
-        uint64_t idx = si[t] < (uint64_t)N ? si[t] : 0;
+    __shared__ uint64_t sk[MERGE_N];
+    __shared__ uint64_t si[MERGE_N];
+    __shared__ float sf[MERGE_N];
+    for (int t = threadIdx.x; t < MERGE_N; t += blockDim.x) {
+        if (t < k_run) {
+            const tno_candidate c = out[t];
+            sk[t] = ordered_key(c.snr);
+            si[t] = ((uint64_t)c.traj * (uint64_t)HW) + (uint64_t)c.y * (uint64_t)W + (uint64_t)c.x;
+            sf[t] = c.flux;
+        } else if (t < k_run + k_new) {
+            const uint64_t c = cand[2 * (t - k_run) + 1];
+            const uint64_t li = c < (uint64_t)N ? c : 0;   // (always below N)
+            sk[t] = cand[2 * (t - k_run)];
+            si[t] = (uint64_t)rows[li / (uint64_t)HW] * (uint64_t)HW + li % (uint64_t)HW;
+            sf[t] = flux[li];
+        } else {
+            sk[t] = 0u;      // padding: the smallest key and the largest index
+            si[t] = ~0ull;
+            sf[t] = 0.0f;
+        }
+    }
+    __syncthreads();
+    // bitonic sort into (key descending, index ascending); the thread owning
+    // slot t compares it with its partner t ^ stride when that is larger
+    for (int size = 2; size <= MERGE_N; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < MERGE_N; t += blockDim.x) {
+                const int p = t ^ stride;
+                if (p > t) {
+                    const bool t_before_p = sk[t] > sk[p] || (sk[t] == sk[p] && si[t] < si[p]);
+                    const bool ascending = (t & size) == 0;
+                    if (ascending != t_before_p) {
+                        const uint64_t a = sk[t]; sk[t] = sk[p]; sk[p] = a;
+                        const uint64_t b = si[t]; si[t] = si[p]; si[p] = b;
+                        const float c = sf[t]; sf[t] = sf[p]; sf[p] = c;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < k_out; t += blockDim.x) {
         tno_candidate c;
         c.snr = key_to_float((uint32_t)sk[t]);
-        c.flux = flux[idx];
-        c.traj = (int32_t)(idx / (uint64_t)HW);
-        uint32_t p = (uint32_t)(idx % (uint64_t)HW);
-        c.y = (int32_t)(p / (uint32_t)W);
-        c.x = (int32_t)(p % (uint32_t)W);
+        c.flux = sf[t];
+        c.traj = (int32_t)(si[t] / (uint64_t)HW);
+        const uint64_t p = si[t] % (uint64_t)HW;
+        c.y = (int32_t)(p / (uint64_t)W);
+        c.x = (int32_t)(p % (uint64_t)W);
         out[t] = c;
     }
 }
@@ -1351,13 +1445,14 @@ static void topk_select(hipStream_t st, const float *vals, int64_t N, int k, Top
     hipLaunchKernelGGL(k_topk_ties, dim3((unsigned)n_chunks), dim3(256), 0, st, vals, N, k, state, chunk_cnt, cand);
 }
 
-hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int64_t N, int HW,
-                       int W, int k, TopkState *state, uint32_t *chunk_cnt, int64_t n_chunks,
-                       uint64_t *cand, void *topk_out)
+hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int64_t N, int64_t HW,
+                       int W, const int32_t *rows, int k, int k_run, TopkState *state, uint32_t *chunk_cnt,
+                       int64_t n_chunks, uint64_t *cand, void *topk_out)
 {
-    topk_select(st, snr, N, k, state, chunk_cnt, n_chunks, cand);
-    hipLaunchKernelGGL(k_topk_final, dim3(1), dim3(TNO_MAX_TOPK), 0, st, flux, N, k, HW, W, cand,
-                       (tno_candidate *)topk_out);
+    const int k_new = (int)std::min<int64_t>(k, N);
+    topk_select(st, snr, N, k_new, state, chunk_cnt, n_chunks, cand);
+    hipLaunchKernelGGL(k_topk_merge, dim3(1), dim3(1024), 0, st, k_new, k_run, std::min(k, k_run + k_new), N,
+                       HW, W, rows, cand, flux, (tno_candidate *)topk_out);
     return hipGetLastError();
 }
 
@@ -1509,7 +1604,7 @@ __global__ void k_count_above(int64_t N, const float *__restrict__ sig, float th
 __global__ __launch_bounds__(1024) void k_detect_final(
     int64_t HW, int W, int k, float thr, const uint64_t *__restrict__ cand,
     const float *__restrict__ best_snr, const int32_t *__restrict__ best_traj,
-    const float *__restrict__ flux, tno_detection *__restrict__ out, int32_t *n_out)
+    const float *__restrict__ best_flux, tno_detection *__restrict__ out, int32_t *n_out)
 {
     __shared__ uint64_t sk[TNO_MAX_TOPK];
     __shared__ uint64_t si[TNO_MAX_TOPK];
@@ -1526,7 +1621,7 @@ __global__ __launch_bounds__(1024) void k_detect_final(
             tno_detection d;
             d.significance = g;
             d.snr = best_snr[p];
-            d.flux = flux[(uint64_t)j * HW + p];
+            d.flux = best_flux[p];
             d.traj = j;
             d.y = (int32_t)(p / (uint64_t)W);
             d.x = (int32_t)(p % (uint64_t)W);
@@ -1546,7 +1641,7 @@ int64_t significance_block_values(int H, int W)
 }
 
 hipError_t launch_significance(hipStream_t st, int H, int W, int box, float thr, int k,
-                               const float *best_snr, const int32_t *best_traj, const float *flux,
+                               const float *best_snr, const int32_t *best_traj, const float *best_flux,
                                double *r1, double *r2, double *b1, double *b2, float *sig,
                                TopkState *state, uint32_t *chunk_cnt, int64_t n_chunks,
                                uint64_t *cand, tno_detection *det, int32_t *counts)
@@ -1565,7 +1660,7 @@ hipError_t launch_significance(hipStream_t st, int H, int W, int box, float thr,
     if (k > 0) {
         topk_select(st, sig, HW, k, state, chunk_cnt, n_chunks, cand);
         hipLaunchKernelGGL(k_detect_final, dim3(1), dim3(TNO_MAX_TOPK), 0, st, HW, W, k, thr, cand,
-                           best_snr, best_traj, flux, det, counts + 1);
+                           best_snr, best_traj, best_flux, det, counts + 1);
     }
     return hipGetLastError();
 }

@@ -57,6 +57,9 @@ Fail fail(int code, const char *fmt, ...)
 
 constexpr int PAD_CAP = 512;      // largest zero border of the staged stack, per side
 constexpr size_t ALIGN = 256;
+// Device bytes of a slab's normaliser and unrequested maps (a slab holds at
+// least one trajectory).
+constexpr size_t SLAB_BYTES = 2ull << 30;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -89,19 +92,33 @@ struct Plan {
     int ntx = 0, nty = 0, ntiles = 0;
     int variant = 0, tblock = 1;      // search tile shape and trajectory block of the work order
     int ntiles_max = 0;               // tiles of the smallest shape (sizes the tile-key buffer)
-    std::vector<int32_t> perm;        // velocity-sorted search order
+    std::vector<int32_t> perm;        // search order (velocity-sorted)
     // normaliser launches: [0] trails stored by columns, [1] by rows (run in
     // the transposed image); each with its zero-bordered FP64 ivar map
     struct LamLaunch {
-        int nj = 0, joff = 0;          // trajectories, first index in `jlist`
+        int nj = 0;                    // trajectories (all slabs)
         int Hf = 0, Wf = 0;            // image in the launch's frame
         int ntx = 0, nty = 0;
         int Pyt = 0, Pxl = 0, Hq = 0, Wq = 0;
         size_t o_map = 0;
     } lam[2];
-    std::vector<int32_t> jlist;       // trajectories of launch 0, then of launch 1
+    // Trajectory slabs: consecutive runs of the search order.  The normaliser
+    // and the SNR and flux maps exist for one slab at a time, a row per
+    // trajectory of the slab in increasing trajectory number; the reductions
+    // merge slab after slab, and maps the caller asked for receive each
+    // slab's rows.
+    struct Slab {
+        int a0 = 0, a1 = 0;            // search positions a0 .. a1-1 (perm, rows)
+        int joff[2] = {0, 0}, nj[2] = {0, 0};   // its normaliser launches in `jlist`
+    };
+    std::vector<Slab> slabs;
+    int jslab = 0;                    // trajectories of the largest slab
+    std::vector<int32_t> rows;        // per slab: its trajectories in increasing order (map rows)
+    std::vector<int32_t> jrow;        // [J] row of each trajectory in its slab's maps
+    std::vector<int32_t> jlist;       // per slab: trajectories of launch 0, then of launch 1
     int64_t N = 0, n_chunks = 0;
-    bool own_snr = true, own_flux = true;
+    bool full_snr = false, full_flux = false;   // maps with every trajectory's row (asked for)
+    bool own_snr = false, own_flux = false;     // ... held in the arena (host outputs)
     int box = 0, kdet = 0;            // significance window side; detections wanted
     float thr = 0.0f;
     bool stack_in_arena = false;      // host residuals copied into the arena (no stack_key)
@@ -110,7 +127,8 @@ struct Plan {
     size_t o_R = 0, o_scales = 0, o_sigma = 0, o_times = 0, o_vel = 0, o_Z = 0, o_iv32 = 0,
            o_iv64 = 0, o_tab32 = 0, o_tab64 = 0, o_trail = 0, o_colmeta = 0, o_kvals = 0,
            o_err = 0, o_lam = 0, o_snr = 0, o_flux = 0, o_tkeys = 0, o_tstate = 0, o_chunks = 0,
-           o_cand = 0, o_tmax = 0, o_topk = 0, o_best = 0, o_bestj = 0, o_perm = 0, o_r1 = 0,
+           o_cand = 0, o_tmax = 0, o_topk = 0, o_best = 0, o_bestj = 0, o_bestf = 0, o_perm = 0, o_rows = 0,
+           o_jrow = 0, o_snr_full = 0, o_flux_full = 0, o_r1 = 0,
            o_r2 = 0, o_b1 = 0, o_b2 = 0, o_sig = 0, o_det = 0, o_counts = 0, o_prf = 0, o_jit = 0,
            o_jl = 0, bytes = 0;
 };
@@ -222,7 +240,7 @@ void set_search_shape(Plan &p, int v, int tblock)
 
 // Build the plan from host copies of times, velocities and jitter (NULL: none).
 Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
-               const double *vel, const double *jit, Plan &p)
+               const double *vel, const double *jit, Plan &p, size_t slab_bytes = SLAB_BYTES)
 {
     Fail f = check_shape(r, o);
     if (f.code)
@@ -406,29 +424,25 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
         if (footprint(dir) < footprint(p.perm))
             p.perm = dir;
     }
-    p.jlist.clear();
     for (int o = 0; o < 2; ++o) {
         auto &L = p.lam[o];
-        L.joff = (int)p.jlist.size();
-        for (int j = 0; j < p.J; ++j)
-            if (p.trail[j].tr == o)
-                p.jlist.push_back(j);
-        L.nj = (int)p.jlist.size() - L.joff;
+        L.nj = 0;
         L.Hf = o ? W : H;
         L.Wf = o ? H : W;
         L.ntx = (L.Wf + tno::LAMBDA_TX - 1) / tno::LAMBDA_TX;
         L.nty = (L.Hf + tno::LAMBDA_TY - 1) / tno::LAMBDA_TY;
-        if ((double)L.ntx * L.nty * L.nj > 2.0e9)
-            return fail(TNO_E_INVAL, "too many normaliser work items");
         // In the launch's frame the normaliser reads ivar at x + q (x below
         // ntx * TX, q a major offset of a box) and, along a run [lo, lo +
         // len) of minor offsets inside [qy_lo, qy_hi], rows y0 + lo ... y0 +
         // lo + roundC(len) + R - 2 (C = LAMBDA_CHUNK) for a wave whose first
         // row y0 is at most nty * TY - R, i.e. at most nty * TY + qy_hi + C -
-        // 2.  The border covers them all.
+        // 2.  The border covers them all (every slab's launches).
         int qxmin = 0, qxmax = 0, qymin = 0, qymax = 0;
-        for (int i = 0; i < L.nj; ++i) {
-            const auto &ti = p.trail[p.jlist[L.joff + i]];
+        for (int j = 0; j < p.J; ++j) {
+            const auto &ti = p.trail[j];
+            if (ti.tr != o)
+                continue;
+            ++L.nj;
             if (ti.ncols <= 0)
                 continue;
             qxmin = std::min(qxmin, ti.qx0);
@@ -436,6 +450,8 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
             qymin = std::min(qymin, ti.qy_lo);
             qymax = std::max(qymax, ti.qy_hi);
         }
+        if ((double)L.ntx * L.nty * L.nj > 2.0e9)
+            return fail(TNO_E_INVAL, "too many normaliser work items");
         L.Pxl = -qxmin;
         const int pxr = std::max(0, L.ntx * tno::LAMBDA_TX + qxmax - L.Wf);
         L.Pyt = -qymin;
@@ -443,14 +459,43 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
         L.Wq = L.Wf + L.Pxl + pxr;
         L.Hq = L.Hf + L.Pyt + pyb;
     }
-    p.N = (int64_t)p.J * H * W;
-    p.k = (int)std::min<int64_t>(r->top_k, p.N);
-    p.n_chunks = (p.N + tno::TOPK_CHUNK - 1) / tno::TOPK_CHUNK;
     p.box = r->sig_box;
     p.thr = r->sig_threshold;
     p.kdet = (int)std::min<int64_t>(o->max_detections, (int64_t)p.H * p.W);
-    p.own_snr = !(p.dev && o->snr);
-    p.own_flux = !(p.dev && o->flux);
+    p.full_snr = o->snr != nullptr;
+    p.full_flux = o->flux != nullptr;
+    p.own_snr = p.full_snr && !p.dev;
+    p.own_flux = p.full_flux && !p.dev;
+    // trajectory slabs: runs of the search order, as many trajectories per
+    // slab as keep Lam and the slab's maps within slab_bytes, balanced
+    {
+        const size_t per = (size_t)H * W * 16;
+        int js = (int)std::max<size_t>(1, std::min<size_t>((size_t)p.J, slab_bytes / per));
+        const int ns = (p.J + js - 1) / js;
+        p.jslab = (p.J + ns - 1) / ns;
+        p.slabs.assign(ns, Plan::Slab{});
+        p.rows.assign(p.perm.begin(), p.perm.end());
+        p.jrow.assign(p.J, 0);
+        p.jlist.clear();
+        for (int s = 0; s < ns; ++s) {
+            auto &sl = p.slabs[s];
+            sl.a0 = s * p.jslab;
+            sl.a1 = std::min(p.J, sl.a0 + p.jslab);
+            std::sort(p.rows.begin() + sl.a0, p.rows.begin() + sl.a1);
+            for (int a = sl.a0; a < sl.a1; ++a)
+                p.jrow[p.rows[a]] = a - sl.a0;
+            for (int o2 = 0; o2 < 2; ++o2) {
+                sl.joff[o2] = (int)p.jlist.size();
+                for (int a = sl.a0; a < sl.a1; ++a)
+                    if (p.trail[p.rows[a]].tr == o2)
+                        p.jlist.push_back(p.rows[a]);
+                sl.nj[o2] = (int)p.jlist.size() - sl.joff[o2];
+            }
+        }
+    }
+    p.N = (int64_t)p.J * H * W;
+    p.k = (int)std::min<int64_t>(r->top_k, p.N);
+    p.n_chunks = ((int64_t)p.jslab * H * W + tno::TOPK_CHUNK - 1) / tno::TOPK_CHUNK;
 
     // arena layout
     const size_t HW = (size_t)H * W, T = (size_t)p.T, J = (size_t)p.J;
@@ -490,13 +535,18 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     p.o_colmeta = take((size_t)p.n_colmeta * 8);
     p.o_kvals = take((size_t)p.n_kvals * 8);
     p.o_err = take(4);
-    p.o_lam = take(J * HW * 8);
+    const size_t JS = (size_t)p.jslab;
+    p.o_lam = take(JS * HW * 8);
+    p.o_snr = take(JS * HW * 4);
+    p.o_flux = take(JS * HW * 4);
     if (p.own_snr)
-        p.o_snr = take(J * HW * 4);
+        p.o_snr_full = take(J * HW * 4);
     if (p.own_flux)
-        p.o_flux = take(J * HW * 4);
+        p.o_flux_full = take(J * HW * 4);
     p.o_tkeys = take(J * p.ntiles_max * 8);
     p.o_perm = take(J * 4);
+    p.o_rows = take(J * 4);
+    p.o_jrow = take(J * 4);
     p.o_tstate = take(sizeof(tno::TopkState));
     p.o_chunks = take((size_t)p.n_chunks * 4);
     p.o_cand = take((size_t)TNO_MAX_TOPK * 16);
@@ -504,6 +554,7 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     p.o_topk = take((size_t)TNO_MAX_TOPK * sizeof(tno_candidate));
     p.o_best = take(HW * 4);
     p.o_bestj = take(HW * 4);
+    p.o_bestf = take(HW * 4);
     p.o_counts = take(16);
     if (p.box > 0) {
         p.o_r1 = take(HW * 8);
@@ -539,7 +590,10 @@ struct Request {
     size_t arena_bytes = 0;
     Stack *stack = nullptr;
     hipStream_t stream = nullptr;
-    hipEvent_t ev[6] = {};   // phase boundaries; ev[0] start, ev[5] end
+    hipEvent_t ev[6] = {};   // ev[0] start, ev[1] weighting done, ev[2] table and trail done, ev[5] end
+    // per slab s: sev[3s] normaliser start, sev[3s+1] its end (search start),
+    // sev[3s+2] search end
+    std::vector<hipEvent_t> sev;
     std::chrono::steady_clock::time_point t_submit;
     uint64_t updates = 0;
     hipGraphExec_t exec = nullptr;   // graph mode: the executable graph this request ran
@@ -550,7 +604,8 @@ struct Request {
     // TNO_CFG_BATCH: end of the preparation on `stream`, and the next search
     // work item not yet handed to a step
     hipEvent_t prep_done = nullptr;
-    int next_item = 0;
+    int slab = 0;                    // the slab being searched
+    int next_item = 0;               // (of that slab)
     bool end_recorded = false;       // ev[5] recorded (a batched request records it late)
 };
 
@@ -611,6 +666,7 @@ struct tno_search {
                                        // (their actual sizes, so in_use + cache.held is what
                                        // the handle holds on the device)
     int max_inflight = 64;
+    size_t slab_bytes = SLAB_BYTES;    // device bytes of a request's trajectory slab
     uint64_t next_ticket = 1;
     uint64_t tick = 0;
     std::mutex mu;
@@ -776,9 +832,27 @@ Inputs inputs_of(const Request *q, const tno_request *r)
             return e;           \
     } while (0)
 
-tno::SearchArgs search_args(const Request *q, float *snr, float *flux, int nframes, int kstride = 1)
+// The maps of the slab being searched (a row per trajectory of the slab),
+// and the maps with a row per trajectory that the caller asked for (the
+// caller's device maps, or the arena's copies of host maps), or NULL.
+float *snr_rows(const Request *q) { return at<float>(q->arena, q->plan.o_snr); }
+float *flux_rows(const Request *q) { return at<float>(q->arena, q->plan.o_flux); }
+float *snr_full(const Request *q)
 {
     const Plan &p = q->plan;
+    return !p.full_snr ? nullptr : p.own_snr ? at<float>(q->arena, p.o_snr_full) : q->out.snr;
+}
+float *flux_full(const Request *q)
+{
+    const Plan &p = q->plan;
+    return !p.full_flux ? nullptr : p.own_flux ? at<float>(q->arena, p.o_flux_full) : q->out.flux;
+}
+
+// Search arguments of slab s (its first nframes frames, every kstride-th).
+tno::SearchArgs search_args(const Request *q, int s, int nframes, int kstride = 1)
+{
+    const Plan &p = q->plan;
+    const Plan::Slab &sl = p.slabs[s];
     void *A = q->arena;
     tno::SearchArgs sa;
     sa.Z4 = p.direct ? nullptr : at<float4>(A, p.o_Z);
@@ -790,29 +864,27 @@ tno::SearchArgs search_args(const Request *q, float *snr, float *flux, int nfram
     sa.nqx = (p.W + TNO_QTILE - 1) / TNO_QTILE;
     sa.tab32 = at<int32_t>(A, p.o_tab32);
     sa.lam = at<double>(A, p.o_lam);
-    sa.snr = snr;
-    sa.flux = flux;
+    sa.snr = snr_rows(q);
+    sa.flux = flux_rows(q);
     sa.tile_keys = at<uint64_t>(A, p.o_tkeys);
-    sa.perm = at<int32_t>(A, p.o_perm);
+    sa.perm = at<int32_t>(A, p.o_perm) + sl.a0;
+    sa.jrow = at<int32_t>(A, p.o_jrow);
     sa.H = p.H;
     sa.W = p.W;
     sa.T = p.T;
-    sa.J = p.J;
+    sa.J = sl.a1 - sl.a0;
     sa.Hp = p.Hp;
     sa.Wp4 = p.Wp4;
     sa.Pt = p.Pt;
     sa.Pl = p.Pl;
     sa.ntx = p.ntx;
     sa.nty = p.nty;
-    sa.n_items = p.ntiles * p.J;
-    sa.tblock = p.tblock;
+    sa.n_items = p.ntiles * sa.J;
+    sa.tblock = std::min(p.tblock, sa.J);
     sa.nframes = nframes;
     sa.kstride = kstride;
     return sa;
 }
-
-float *snr_map(Request *q) { return q->plan.own_snr ? at<float>(q->arena, q->plan.o_snr) : q->out.snr; }
-float *flux_map(Request *q) { return q->plan.own_flux ? at<float>(q->arena, q->plan.o_flux) : q->out.flux; }
 
 // Enqueue what precedes the kernels: the wait on a resident stack's upload,
 // the start event, and the host-side trail layout and search order.  (Kept
@@ -832,11 +904,18 @@ hipError_t enqueue_pre(Request *q)
                        hipMemcpyHostToDevice, st));
     TRY(hipMemcpyAsync(at<void>(A, p.o_jl), p.jlist.data(), p.jlist.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice, st));
+    TRY(hipMemcpyAsync(at<void>(A, p.o_rows), p.rows.data(), p.rows.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, st));
+    TRY(hipMemcpyAsync(at<void>(A, p.o_jrow), p.jrow.data(), p.jrow.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, st));
     return hipSuccess;
 }
 
+hipError_t enqueue_lambda(Request *q, int s, bool events);
+
 // Enqueue the kernels before the numerator search: weighting, table, trail,
-// Lam; `events`: record the phase boundaries (not inside a captured graph).
+// the first slab's Lam; `events`: record the phase boundaries (not inside a
+// captured graph).
 hipError_t enqueue_front(Request *q, const tno_request *r, bool events)
 {
     const Plan &p = q->plan;
@@ -866,9 +945,23 @@ hipError_t enqueue_front(Request *q, const tno_request *r, bool events)
                           at<double>(A, p.o_kvals), at<int32_t>(A, p.o_err)));
     if (events)
         TRY(hipEventRecord(q->ev[2], st));
+    return enqueue_lambda(q, 0, events);
+}
+
+// The normaliser of slab s (into the slab's Lam rows); `events`: record its
+// start and end.
+hipError_t enqueue_lambda(Request *q, int s, bool events)
+{
+    const Plan &p = q->plan;
+    const Plan::Slab &sl = p.slabs[s];
+    hipStream_t st = q->stream;
+    void *A = q->arena;
+    hipError_t e;
+    if (events)
+        TRY(hipEventRecord(q->sev[3 * s], st));
     for (int o = 0; o < 2; ++o) {
         const auto &L = p.lam[o];
-        if (L.nj == 0)
+        if (sl.nj[o] == 0)
             continue;
         tno::LambdaArgs la;
         la.info = at<tno::TrailInfo>(A, p.o_trail);
@@ -876,15 +969,16 @@ hipError_t enqueue_front(Request *q, const tno_request *r, bool events)
         la.kvals = at<double>(A, p.o_kvals);
         la.ivar64 = at<double>(A, L.o_map);
         la.lam = at<double>(A, p.o_lam);
-        la.jlist = at<int32_t>(A, p.o_jl) + L.joff;
+        la.jrow = at<int32_t>(A, p.o_jrow);
+        la.jlist = at<int32_t>(A, p.o_jl) + sl.joff[o];
         la.H = L.Hf;
         la.W = L.Wf;
         la.H0 = p.H;
         la.W0 = p.W;
-        la.nj = L.nj;
+        la.nj = sl.nj[o];
         la.ntx = L.ntx;
         la.nty = L.nty;
-        la.n_items = L.ntx * L.nty * L.nj;
+        la.n_items = L.ntx * L.nty * sl.nj[o];
         la.Pyt = L.Pyt;
         la.Pxl = L.Pxl;
         la.Wq = L.Wq;
@@ -892,47 +986,76 @@ hipError_t enqueue_front(Request *q, const tno_request *r, bool events)
         TRY(tno::launch_lambda(st, la));
     }
     if (events)
-        TRY(hipEventRecord(q->ev[3], st));
+        TRY(hipEventRecord(q->sev[3 * s + 1], st));
     return hipSuccess;
 }
 
-// Enqueue the numerator search, the reductions and the output copies;
+// Enqueue the search of every slab with its reductions (the first slab's
+// Lam is already enqueued), then the significance pass and output copies;
 // `events`: record the phase boundaries and the end event.
-hipError_t enqueue_reduce(Request *q, bool events);
+hipError_t enqueue_slab_reduce(Request *q, int s);
+hipError_t enqueue_final(Request *q, bool events);
 
 hipError_t enqueue_back(Request *q, bool events)
 {
     const Plan &p = q->plan;
     hipError_t e;
-    const tno::SearchArgs sa = search_args(q, snr_map(q), flux_map(q), p.T);
-    TRY(tno::launch_search(q->stream, p.S, p.sep, p.variant, sa));
-    if (events)
-        TRY(hipEventRecord(q->ev[4], q->stream));
-    return enqueue_reduce(q, events);
+    for (int s = 0; s < (int)p.slabs.size(); ++s) {
+        if (s > 0)
+            TRY(enqueue_lambda(q, s, events));
+        TRY(tno::launch_search(q->stream, p.S, p.sep, p.variant, search_args(q, s, p.T)));
+        if (events)
+            TRY(hipEventRecord(q->sev[3 * s + 2], q->stream));
+        TRY(enqueue_slab_reduce(q, s));
+    }
+    return enqueue_final(q, events);
 }
 
-// The reductions and output copies after the search (on the request's
-// stream); `events`: record the end event.
-hipError_t enqueue_reduce(Request *q, bool events)
+// After slab s's search (on the request's stream): its rows into the maps
+// the caller asked for, its trajectories' peaks, and the bank maximum and
+// top-k merged with the slab's maps.
+hipError_t enqueue_slab_reduce(Request *q, int s)
+{
+    const Plan &p = q->plan;
+    const Plan::Slab &sl = p.slabs[s];
+    hipStream_t st = q->stream;
+    void *A = q->arena;
+    const int nj = sl.a1 - sl.a0;
+    const int64_t HW = (int64_t)p.H * p.W;
+    const int32_t *rows = at<int32_t>(A, p.o_rows) + sl.a0;
+    const float *snr = snr_rows(q);
+    const float *flux = flux_rows(q);
+    hipError_t e;
+    if (p.full_snr)
+        TRY(tno::launch_rows_out(st, nj, HW, rows, snr, snr_full(q)));
+    if (p.full_flux)
+        TRY(tno::launch_rows_out(st, nj, HW, rows, flux, flux_full(q)));
+    TRY(tno::launch_trajmax(st, nj, p.ntiles, p.W, (int)HW, rows, at<uint64_t>(A, p.o_tkeys), snr, flux,
+                            at<void>(A, p.o_tmax)));
+    TRY(tno::launch_best(st, nj, HW, rows, s == 0, snr, flux, at<float>(A, p.o_best),
+                         at<int32_t>(A, p.o_bestj), at<float>(A, p.o_bestf)));
+    if (p.k > 0) {
+        const int k_run = (int)std::min<int64_t>(p.k, (int64_t)sl.a0 * HW);   // kept from earlier slabs
+        TRY(tno::launch_topk(st, snr, flux, (int64_t)nj * HW, HW, p.W, rows, p.k, k_run,
+                             at<tno::TopkState>(A, p.o_tstate), at<uint32_t>(A, p.o_chunks), p.n_chunks,
+                             at<uint64_t>(A, p.o_cand), at<void>(A, p.o_topk)));
+    }
+    return hipSuccess;
+}
+
+// The significance pass and the output copies after the last slab;
+// `events`: record the end event.
+hipError_t enqueue_final(Request *q, bool events)
 {
     const Plan &p = q->plan;
     hipStream_t st = q->stream;
     void *A = q->arena;
-    float *snr = snr_map(q);
-    float *flux = flux_map(q);
     const int HW = p.H * p.W;
-    const tno::SearchArgs sa = search_args(q, snr, flux, p.T);
     hipError_t e;
-    TRY(tno::launch_trajmax(st, p.J, p.ntiles, p.W, HW, sa.tile_keys, snr, flux, at<void>(A, p.o_tmax)));
-    TRY(tno::launch_best(st, p.J, HW, snr, at<float>(A, p.o_best), at<int32_t>(A, p.o_bestj)));
-    if (p.k > 0)
-        TRY(tno::launch_topk(st, snr, flux, p.N, HW, p.W, p.k, at<tno::TopkState>(A, p.o_tstate),
-                             at<uint32_t>(A, p.o_chunks), p.n_chunks, at<uint64_t>(A, p.o_cand),
-                             at<void>(A, p.o_topk)));
     TRY(tno::launch_zero(st, at<int32_t>(A, p.o_counts), 4));
     if (p.box > 0)
         TRY(tno::launch_significance(st, p.H, p.W, p.box, p.thr, p.kdet, at<float>(A, p.o_best),
-                                     at<int32_t>(A, p.o_bestj), flux, at<double>(A, p.o_r1),
+                                     at<int32_t>(A, p.o_bestj), at<float>(A, p.o_bestf), at<double>(A, p.o_r1),
                                      at<double>(A, p.o_r2), at<double>(A, p.o_b1),
                                      at<double>(A, p.o_b2), at<float>(A, p.o_sig),
                                      at<tno::TopkState>(A, p.o_tstate), at<uint32_t>(A, p.o_chunks),
@@ -984,9 +1107,10 @@ hipError_t autotune(tno_search *h, Request *q)
         float ms;
     };
     std::vector<Cand> cands;
-    std::vector<int> tbs = {p.J};
+    const int js = p.slabs[0].a1 - p.slabs[0].a0;
+    std::vector<int> tbs = {js};
     for (int tb : {64, 16})
-        if (tb < p.J)
+        if (tb < js)
             tbs.push_back(tb);
     for (int v = 0; v < tno::N_SEARCH_VARIANTS; ++v)
         if (variant_serves(p, v))
@@ -1003,7 +1127,7 @@ hipError_t autotune(tno_search *h, Request *q)
             e = hipEventCreate(&x);
     for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
         set_search_shape(p, cands[i].v, cands[i].tb);
-        const tno::SearchArgs sa = search_args(q, snr_map(q), flux_map(q), probe, kstride);
+        const tno::SearchArgs sa = search_args(q, 0, probe, kstride);   // the first slab
         for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {   // second run is timed
             if (rep == 1)
                 e = hipEventRecord(ev[2 * i], q->stream);
@@ -1037,7 +1161,7 @@ hipError_t autotune(tno_search *h, Request *q)
     if (cands[best].ms > 0.98f * cands[def].ms)
         best = def;
     set_search_shape(p, cands[best].v, cands[best].tb);
-    const double rate = (double)p.J * p.H * p.W * probe / (cands[best].ms * 1e-3);
+    const double rate = (double)js * p.H * p.W * probe / (cands[best].ms * 1e-3);
     h->tuned[shape_class(p)] = {cands[best].v, cands[best].tb, rate};
     h->save_tuning();
     return hipSuccess;
@@ -1057,9 +1181,14 @@ std::string graph_key(const Request *q)
     char buf[256];
     snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %u", p.H, p.W,
              p.T, p.J, p.S, (int)p.sep, p.kind, p.variant, p.tblock, p.dtype, p.k, p.box, p.kdet,
-             (int)p.own_snr, (int)p.own_flux, (int)p.dev, (int)p.jitter, (int)p.direct, p.Hp, p.Wp4,
+             (int)p.full_snr, (int)p.full_flux, (int)p.dev, (int)p.jitter, (int)p.direct, p.Hp, p.Wp4,
              p.lam[0].nj > 0, p.lam[1].nj > 0, copies);
-    return buf;
+    std::string key = buf;
+    for (const auto &sl : p.slabs) {       // the slabs' launches
+        snprintf(buf, sizeof buf, " %d:%d:%d", sl.a1 - sl.a0, sl.nj[0], sl.nj[1]);
+        key += buf;
+    }
+    return key;
 }
 
 // Graph mode: the request's kernels and device copies are captured into a
@@ -1119,8 +1248,10 @@ hipError_t run_graphed(tno_search *h, Request *q, const tno_request *req)
 // items in request order (an equal share of STEP_BLOCKS, at least
 // STEP_CHUNK_MIN), copies the requests' arguments and chunk table into a free
 // descriptor slot and launches once on the next search stream.  The stream
-// of every request in the step waits for the step; a request whose last
-// items were launched gets its reductions queued there.  Cancelled requests
+// of every request in the step waits for the step; a request whose slab's
+// last items were launched gets the slab's reductions queued there, then the
+// next slab's normaliser (the request is ready again when it is done) or the
+// final pass.  Cancelled requests
 // leave the queue with their end event recorded after their launched steps.
 // Called with the handle's lock held.
 hipError_t pump(tno_search *h)
@@ -1176,9 +1307,9 @@ hipError_t pump(tno_search *h)
         int n = 0, nblocks = 0;
         for (Request *q : take) {
             const Plan &p = q->plan;
-            const int n_items = p.ntiles * p.J;
+            const int n_items = p.ntiles * (p.slabs[q->slab].a1 - p.slabs[q->slab].a0);
             const int cnt = std::min(share, n_items - q->next_item);
-            args[n] = search_args(q, snr_map(q), flux_map(q), p.T);
+            args[n] = search_args(q, q->slab, p.T);
             ent[n] = {nblocks, (cnt + 7) / 8 * 8, q->next_item, cnt};
             nblocks += ent[n].nblk;
             ++n;
@@ -1203,10 +1334,24 @@ hipError_t pump(tno_search *h)
             h->n_step_items += ent[i].count;
             if ((e = hipStreamWaitEvent(q->stream, sl.done, 0)) != hipSuccess)
                 return e;
-            if (q->next_item == q->plan.ntiles * q->plan.J) {
+            const Plan &p = q->plan;
+            const int s = q->slab;
+            if (q->next_item < p.ntiles * (p.slabs[s].a1 - p.slabs[s].a0))
+                continue;
+            // the slab's last items: its reductions, then the next slab's
+            // normaliser (its items are ready when that is done) or the end
+            if ((e = hipEventRecord(q->sev[3 * s + 2], q->stream)) != hipSuccess ||
+                (e = enqueue_slab_reduce(q, s)) != hipSuccess)
+                return e;
+            if (s + 1 < (int)p.slabs.size()) {
+                q->slab = s + 1;
+                q->next_item = 0;
+                if ((e = enqueue_lambda(q, s + 1, true)) != hipSuccess ||
+                    (e = hipEventRecord(q->prep_done, q->stream)) != hipSuccess)
+                    return e;
+            } else {
                 h->ready.erase(std::find(h->ready.begin(), h->ready.end(), q));
-                if ((e = hipEventRecord(q->ev[4], q->stream)) != hipSuccess ||
-                    (e = enqueue_reduce(q, true)) != hipSuccess)
+                if ((e = enqueue_final(q, true)) != hipSuccess)
                     return e;
             }
         }
@@ -1228,6 +1373,9 @@ void release(tno_search *hd, Request *q)
     for (hipEvent_t &e : q->ev)
         if (e)
             (void)hipEventDestroy(e);
+    for (hipEvent_t &e : q->sev)
+        if (e)
+            (void)hipEventDestroy(e);
     if (q->prep_done)
         (void)hipEventDestroy(q->prep_done);
     delete q;
@@ -1247,8 +1395,8 @@ hipError_t finish_outputs(Request *q)
         if (dst && e == hipSuccess)
             e = hipMemcpy(dst, at<void>(A, off), bytes, hipMemcpyDeviceToHost);
     };
-    cp(o.snr, p.o_snr, J * HW * 4);
-    cp(o.flux, p.o_flux, J * HW * 4);
+    cp(o.snr, p.o_snr_full, J * HW * 4);
+    cp(o.flux, p.o_flux_full, J * HW * 4);
     cp(o.best_snr, p.o_best, HW * 4);
     cp(o.best_traj, p.o_bestj, HW * 4);
     cp(o.traj_max, p.o_tmax, J * sizeof(tno_peak));
@@ -1337,6 +1485,7 @@ int tno_search_create(const tno_config *cfg, tno_search **out_handle)
     }
     h->device = cfg->device;
     h->max_inflight = cfg->max_inflight > 0 ? cfg->max_inflight : 64;
+    h->slab_bytes = cfg->slab_bytes ? (size_t)cfg->slab_bytes : SLAB_BYTES;
     if (cfg->stream) {
         h->streams.push_back((hipStream_t)cfg->stream);
     } else {
@@ -1460,7 +1609,7 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
         set_last(fail(TNO_E_NOMEM, "out of host memory"));
         return TNO_E_NOMEM;
     }
-    f = make_plan(req, out, times, vel, jit, q->plan);
+    f = make_plan(req, out, times, vel, jit, q->plan, h->slab_bytes);
     if (f.code) {
         delete q;
         set_last(f);
@@ -1509,11 +1658,13 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
         return TNO_E_NOMEM;
     }
     h->in_use += q->arena_bytes;
-    for (hipEvent_t &ev : q->ev)
-        if ((e = hipEventCreate(&ev)) != hipSuccess) {
-            release(h, q);
-            return hip_fail(e, "hipEventCreate", nullptr, 0);
-        }
+    q->sev.assign(3 * p.slabs.size(), nullptr);
+    for (hipEvent_t *ev : {q->ev, q->sev.data()})
+        for (size_t i = 0, n = ev == q->ev ? 6 : q->sev.size(); i < n; ++i)
+            if ((e = hipEventCreate(&ev[i])) != hipSuccess) {
+                release(h, q);
+                return hip_fail(e, "hipEventCreate", nullptr, 0);
+            }
     const size_t HW = (size_t)p.H * p.W;
     const size_t rbytes = (size_t)p.T * HW * elem_bytes(p.dtype);
     const size_t sbytes = p.dtype == TNO_F32 ? 0 : (size_t)p.T * ((p.H + 63) / 64) * ((p.W + 63) / 64) * 4;
@@ -1671,10 +1822,21 @@ int tno_search_poll(tno_search *h, uint64_t ticket, int32_t timeout_ms, tno_resu
                 float ms = 0.0f;
                 if (hipEventElapsedTime(&ms, q->ev[0], q->ev[5]) == hipSuccess)
                     res.device_ms = ms;
-                double *ph[5] = {&res.prep_ms, &res.table_ms, &res.lambda_ms, &res.search_ms, &res.reduce_ms};
-                for (int i = 0; i < 5 && !q->exec; ++i)      // (graph mode records no phases)
-                    if (hipEventElapsedTime(&ms, q->ev[i], q->ev[i + 1]) == hipSuccess)
-                        *ph[i] = ms;
+                if (!q->exec) {      // (graph mode records no phases)
+                    auto span = [&](hipEvent_t a, hipEvent_t b) {
+                        float t = 0.0f;
+                        return hipEventElapsedTime(&t, a, b) == hipSuccess ? (double)t : 0.0;
+                    };
+                    res.prep_ms = span(q->ev[0], q->ev[1]);
+                    res.table_ms = span(q->ev[1], q->ev[2]);
+                    for (size_t s = 0; s < q->plan.slabs.size(); ++s) {
+                        res.lambda_ms += span(q->sev[3 * s], q->sev[3 * s + 1]);
+                        res.search_ms += span(q->sev[3 * s + 1], q->sev[3 * s + 2]);
+                    }
+                    // the slabs' reductions and the final pass
+                    res.reduce_ms = std::max(0.0, res.device_ms - res.prep_ms - res.table_ms -
+                                                      res.lambda_ms - res.search_ms);
+                }
                 int32_t err = 0, counts[4] = {0, 0, 0, 0};
                 hipError_t e2 = hipMemcpy(&err, at<void>(q->arena, q->plan.o_err), 4, hipMemcpyDeviceToHost);
                 if (e2 == hipSuccess)
@@ -1910,7 +2072,10 @@ int tno_search_run_scratch(const tno_request *req, const tno_outputs *out, void 
             return refuse(fail(TNO_E_DEVICE, "reading jitter: %s", hipGetErrorString(e)));
     }
     Request q;
-    f = make_plan(req, out, times_h.data(), vel_h.data(), req->jitter ? jit_h.data() : nullptr, q.plan);
+    // slabs of at most a quarter of the array, so that the normaliser and
+    // unrequested maps of many trajectories fit by taking them a few at a time
+    f = make_plan(req, out, times_h.data(), vel_h.data(), req->jitter ? jit_h.data() : nullptr, q.plan,
+                  SCRATCH_BYTES / 4);
     if (f.code)
         return refuse(f);
     const Plan &p = q.plan;
@@ -1935,6 +2100,10 @@ int tno_search_run_scratch(const tno_request *req, const tno_outputs *out, void 
         (e = hipMemcpyAsync(at<void>(arena, p.o_perm), p.perm.data(), p.perm.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(at<void>(arena, p.o_jl), p.jlist.data(), p.jlist.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(at<void>(arena, p.o_rows), p.rows.data(), p.rows.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(at<void>(arena, p.o_jrow), p.jrow.data(), p.jrow.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = enqueue_front(&q, req, false)) != hipSuccess || (e = enqueue_back(&q, false)) != hipSuccess) {
         (void)hipStreamSynchronize(st);

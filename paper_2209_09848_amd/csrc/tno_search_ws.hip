@@ -527,7 +527,9 @@ __device__ __forceinline__ void search_ws_item(const SearchArgs &a, int item)
             }
     }
 
-    // epilogue: SNR and flux, and the tile's largest (SNR, -pixel) key
+    // epilogue: SNR and flux (into the trajectory's row of the slab's
+    // maps), and the tile's largest (SNR, -pixel) key
+    const int jr = a.jrow[j];
     uint64_t best = 0;
     const bool lane_out = lane >= 1 && lane <= 62;
 #pragma unroll
@@ -539,7 +541,7 @@ __device__ __forceinline__ void search_ws_item(const SearchArgs &a, int item)
             if (lane_out && y < a.H && x < a.W) {
                 const double nu = acc[o][c];
                 const size_t p = (size_t)y * a.W + x;
-                const size_t mp = (size_t)j * HW + p;
+                const size_t mp = (size_t)jr * HW + p;
                 const double L = a.lam[mp];
                 float snr = 0.0f, flux = 0.0f;
                 if (L > 0.0) {

@@ -117,12 +117,16 @@ class StackPool:
 
 
 def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=16,
-               max_inflight=8, log=None, mode="eager", keep=False, stats=None):
+               max_inflight=8, log=None, mode="eager", keep=False, stats=None, slab_bytes=0,
+               stage_fp32=False):
     """Serve `specs` in arrival order; mode "eager" (each request's kernels on
     a pool stream), "graphs" (each request as a HIP graph) or "batch" (the
     searches of admitted requests share steps).  Returns per-request records
     (keep=True: with each request's outputs and stack key, for checks); a
-    `stats` dict receives the handle's statistics at the end."""
+    `stats` dict receives the handle's statistics at the end; slab_bytes: the
+    handle's trajectory slab size (0: the library's default); stage_fp32: a
+    reduced-precision stack is decoded into an FP32 copy per request
+    (TNO_REQ_STAGE_FP32) instead of searched in place."""
     import torch
     pool = StackPool({s.key: (s.side, s.frames) for s in specs}, dtype, device)
     vel_all = torch.from_numpy(bank).to(device)
@@ -133,7 +137,8 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
     pending = collections.deque(sorted(specs, key=lambda s: s.arrival))
     inflight = {}
     h = tno.Search(0, own_streams=True, max_inflight=max_inflight,
-                   hbm_budget_bytes=int(budget_gb * 1e9), graphs=mode == "graphs", batch=mode == "batch")
+                   hbm_budget_bytes=int(budget_gb * 1e9), graphs=mode == "graphs", batch=mode == "batch",
+                   slab_bytes=slab_bytes)
     t0 = time.perf_counter()
     try:
         while pending or queue or inflight:
@@ -152,7 +157,9 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
                     R, scales = staged[s.key]
                 req = tno.make_request(R, sig if R is not None else None, times, vel, dtype=dtype,
                                        scales=scales, top_k=top_k, stack_key=s.key,
-                                       shape=(s.frames, s.side, s.side))
+                                       shape=(s.frames, s.side, s.side),
+                                       flags=tno.TNO_REQ_DEVICE_PTRS |
+                                       (tno.TNO_REQ_STAGE_FP32 if stage_fp32 else 0))
                 o, out = tno.alloc_outputs(vel.shape[0], s.side, s.side, top_k, device=device,
                                            maps=False)
                 rc, ticket = tno.tno_search_submit(h.h, req, out)

@@ -49,7 +49,8 @@ _vp = ctypes.c_void_p
 class tno_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("stream", _vp), ("tune_cache_path", ctypes.c_char_p)]
+                ("reserved", ctypes.c_uint32), ("stream", _vp), ("tune_cache_path", ctypes.c_char_p),
+                ("slab_bytes", ctypes.c_uint64)]
 
 
 class tno_prf(ctypes.Structure):
@@ -286,12 +287,14 @@ class Search:
 
     def __init__(self, device: int = 0, max_inflight: int = 64, hbm_budget_bytes: int = 0,
                  stream=None, own_streams: bool = False, autotune: bool = False,
-                 tune_cache_path: str | None = None, graphs: bool = False, batch: bool = False):
+                 tune_cache_path: str | None = None, graphs: bool = False, batch: bool = False,
+                 slab_bytes: int = 0):
         """own_streams=True: the library runs requests on its own pool of streams
         (concurrent requests overlap; inputs must be complete before submit);
         otherwise every request runs on `stream` (default: torch's current).
         batch=True (implies own_streams): continuous batching of the searches
-        of admitted requests into shared steps."""
+        of admitted requests into shared steps.  slab_bytes: device bytes of a
+        trajectory slab (0: the library's default)."""
         import torch
         if own_streams or batch:
             stream = 0
@@ -307,6 +310,7 @@ class Search:
         cfg.stream = ctypes.c_void_p(stream) if stream else None
         self._path = tune_cache_path.encode() if tune_cache_path else None
         cfg.tune_cache_path = self._path
+        cfg.slab_bytes = slab_bytes
         self.device = device
         self.h = tno_search_create(cfg)
 

@@ -30,11 +30,16 @@ hipError_t launch_search_step(hipStream_t, int, bool, int, const SearchArgs &, c
 {
     return hipErrorNotSupported;
 }
-hipError_t launch_trajmax(hipStream_t, int, int, int, int, const uint64_t *, const float *, const float *,
-                          void *) { return hipErrorNotSupported; }
-hipError_t launch_best(hipStream_t, int, int, const float *, float *, int32_t *) { return hipErrorNotSupported; }
-hipError_t launch_topk(hipStream_t, const float *, const float *, int64_t, int, int, int, TopkState *,
-                       uint32_t *, int64_t, uint64_t *, void *) { return hipErrorNotSupported; }
+hipError_t launch_trajmax(hipStream_t, int, int, int, int, const int32_t *, const uint64_t *, const float *,
+                          const float *, void *) { return hipErrorNotSupported; }
+hipError_t launch_best(hipStream_t, int, int64_t, const int32_t *, bool, const float *, const float *, float *,
+                       int32_t *, float *) { return hipErrorNotSupported; }
+hipError_t launch_topk(hipStream_t, const float *, const float *, int64_t, int64_t, int, const int32_t *, int,
+                       int, TopkState *, uint32_t *, int64_t, uint64_t *, void *) { return hipErrorNotSupported; }
+hipError_t launch_rows_out(hipStream_t, int, int64_t, const int32_t *, const float *, float *)
+{
+    return hipErrorNotSupported;
+}
 int64_t significance_block_values(int H, int W) { return (int64_t)H * W; }
 hipError_t launch_significance(hipStream_t, int, int, int, float, int, const float *, const int32_t *,
                                const float *, double *, double *, double *, double *, float *, TopkState *,

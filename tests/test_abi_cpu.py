@@ -141,6 +141,35 @@ def test_reduced_precision_footprint_has_no_staged_fp32_copy():
     assert f["bf16_s7"] > f["bf16"] + copy
 
 
+def test_footprint_holds_one_trajectory_slab():
+    """Without caller maps the normaliser and the SNR/flux maps exist for one
+    trajectory slab at a time: a 1024 x 1024 x 1000 BF16 request over 2048
+    trajectories (a resident stack of 2.1 GB) fits in under 12 GB, while the
+    same request asking for both maps needs them whole (2 x J*H*W*4 bytes)."""
+    T, H, W, J = 1000, 1024, 1024, 2048
+    times = 2000.0 + np.arange(T) / 48.0
+    g = np.random.default_rng(0)
+    vel = g.uniform(-0.5, 0.5, (J, 2))
+    req = tno.tno_request()
+    req.height, req.width, req.n_frames, req.dtype = H, W, T, tno.TNO_BF16
+    req.times = times.ctypes.data_as(ctypes.c_void_p)
+    req.t_ref = math.nan
+    req.prf = tno.tno_prf(0, 5, 0.7)
+    req.n_traj = J
+    req.velocities = vel.ctypes.data_as(ctypes.c_void_p)
+    req.stack_key = 7
+    topk = np.zeros((100, 5), np.int32)
+    out = tno.tno_outputs()
+    req.top_k = 100
+    out.topk = topk.ctypes.data_as(ctypes.c_void_p)
+    lean = tno.tno_search_footprint(req, out)
+    assert 0 < lean < 12e9
+    # the map pointers are only checked for presence here (never written)
+    out.snr = out.flux = ctypes.c_void_p(256)
+    full = tno.tno_search_footprint(req, out)
+    assert full - lean >= 2 * J * H * W * 4 - 2 * (2 << 30)
+
+
 def test_create_without_gpu_reports_device_error():
     import torch
     if torch.cuda.is_available():

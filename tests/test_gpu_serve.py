@@ -1,7 +1,8 @@
 """Serving form with continuous batching: a Poisson stream of uneven requests
 (cutouts 256-512 px, 60-160 frames, 8-48 trajectories of the shell bank, BF16
 stacks resident under stack keys) arrives faster than it is served, so the
-searches of admitted requests share steps.  Every result must be the result
+searches of admitted requests share steps (also with trajectory slabs of 8 MiB,
+a request's slabs joining steps one after another).  Every result must be the result
 of the same request run alone, bit for bit; two requests also go to the FP64
 oracle on their dequantized stacks."""
 import numpy as np
@@ -28,8 +29,9 @@ def _alone(pool, spec, bank, dtype):
     return o, res, codes, scales, sig, times
 
 
-@pytest.mark.parametrize("mode", ["batch", "eager"])
-def test_stream_results_equal_alone(mode):
+@pytest.mark.parametrize("mode,slab_bytes", [("batch", 0), ("eager", 0), ("batch", 8 << 20)],
+                         ids=["batch", "eager", "batch_slabs"])
+def test_stream_results_equal_alone(mode, slab_bytes):
     bank, _ = synth.grid_shells()
     shapes = serve.draw_stack_shapes(5, seed=7, sides=[256, 384, 512], frames=(60, 160))
     specs = serve.draw_requests(20, shapes, bank.shape[0], seed=7, jrange=(8, 48))
@@ -37,7 +39,7 @@ def test_stream_results_equal_alone(mode):
     stats = {}
     print("serving 20 requests, mode", mode, flush=True)
     recs = serve.run_stream(specs, bank, dtype="bf16", mode=mode, keep=True, max_inflight=8, top_k=K,
-                            stats=stats)
+                            stats=stats, slab_bytes=slab_bytes)
     print("stats", stats, flush=True)
     assert len(recs) == 20
     if mode == "batch":
