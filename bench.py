@@ -52,9 +52,10 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
-def measured_traffic(updates_per_launch):
-    """HBM bytes per k_search launch from the committed rocprofv3 PMC summary,
-    if it was taken on the current kernel source; else None."""
+def measured_traffic(updates_per_request):
+    """HBM bytes of one request's k_search launches (one per trajectory slab)
+    from the committed rocprofv3 PMC summary, if it was taken on the current
+    kernel source; else None."""
     try:
         with open(PMC_SUMMARY) as f:
             s = json.load(f)
@@ -62,9 +63,9 @@ def measured_traffic(updates_per_launch):
         return None
     if s.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    if s.get("updates_per_launch") != updates_per_launch:
+    if s.get("updates_per_request") != updates_per_request:
         return None
-    return s.get("hbm_bytes_per_launch")
+    return s.get("hbm_bytes_per_request")
 
 
 def measured_copy_GBs():

@@ -116,7 +116,7 @@ typedef struct {
     void *stream;                /* hipStream_t to run on, or NULL for an own stream */
     const char *tune_cache_path; /* text tuning cache read at create and rewritten after each
                                     tuning (one line per arch and shape class), or NULL */
-    uint64_t slab_bytes;         /* device bytes of one trajectory slab (0: 2 GiB).  A request
+    uint64_t slab_bytes;         /* device bytes of one trajectory slab (0: 4 GiB).  A request
                                     searches its trajectories in slabs, consecutive runs of its
                                     velocity-sorted search order: the FP64 normaliser (8 bytes
                                     per start pixel and trajectory) and the slab's SNR and flux

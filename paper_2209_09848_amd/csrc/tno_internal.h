@@ -160,7 +160,8 @@ hipError_t launch_table(hipStream_t st, int J, int T, const double *times, doubl
 hipError_t launch_trail(hipStream_t st, int J, int T, int S, bool sep, const int32_t *tab32,
                         const double *tab64, const TrailInfo *info, int2 *colmeta,
                         double *kvals, int32_t *err);
-hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a);
+// Both orientations' normaliser work in one launch (either may have no items).
+hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a0, const LambdaArgs &a1);
 // Variants 0..N_SEARCH_VARIANTS-1 for the separable stamp of side 5; variant 0
 // for every other (stamp, separability).
 hipError_t launch_search(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a);

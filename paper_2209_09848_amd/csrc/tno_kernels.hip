@@ -418,11 +418,17 @@ hipError_t launch_trail(hipStream_t st, int J, int T, int S, bool sep, const int
 // the launch, so no load is clamped or masked: a wave's loads of one chunk are
 // buffer loads from a scalar base (the chunk's first row at the wave's first
 // column) with the lane's 8-byte column offset and a scalar row offset.
-__global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
+// One launch serves both storage orientations: items below a0.n_items are
+// those of a0 (trails stored by columns), the rest those of a1 (by rows).
+__global__ __launch_bounds__(256) void k_lambda(LambdaArgs a0, LambdaArgs a1)
 {
     constexpr int R = LAMBDA_TY / 4;   // outputs per lane (4 waves stacked)
     constexpr int C = LAMBDA_CHUNK;    // K values per chunk
     int item = xcd_item(blockIdx.x, gridDim.x);
+    const bool second = item >= a0.n_items;
+    const LambdaArgs &a = second ? a1 : a0;
+    if (second)
+        item -= a0.n_items;
     if (item >= a.n_items)
         return;
     const int j = a.jlist[item % a.nj];
@@ -501,9 +507,12 @@ __global__ __launch_bounds__(256) void k_lambda(LambdaArgs a)
     }
 }
 
-hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a)
+hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a0, const LambdaArgs &a1)
 {
-    hipLaunchKernelGGL(k_lambda, dim3(xcd_grid(a.n_items)), dim3(256), 0, st, a);
+    const int n = a0.n_items + a1.n_items;
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_lambda, dim3(xcd_grid(n)), dim3(256), 0, st, a0, a1);
     return hipGetLastError();
 }
 

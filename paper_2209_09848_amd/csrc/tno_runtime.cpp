@@ -57,9 +57,9 @@ Fail fail(int code, const char *fmt, ...)
 
 constexpr int PAD_CAP = 512;      // largest zero border of the staged stack, per side
 constexpr size_t ALIGN = 256;
-// Device bytes of a slab's normaliser and unrequested maps (a slab holds at
+// Device bytes of a trajectory slab's normaliser and maps (a slab holds at
 // least one trajectory).
-constexpr size_t SLAB_BYTES = 2ull << 30;
+constexpr size_t SLAB_BYTES = 4ull << 30;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -467,12 +467,17 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     p.own_snr = p.full_snr && !p.dev;
     p.own_flux = p.full_flux && !p.dev;
     // trajectory slabs: runs of the search order, as many trajectories per
-    // slab as keep Lam and the slab's maps within slab_bytes, balanced
+    // slab as keep Lam and the slab's maps within slab_bytes, in whole
+    // trajectory blocks of the work order where a slab holds one or more
+    // (each block of a launch reads the stack once: a slab cut through a
+    // block would make one more pass over it)
     {
         const size_t per = (size_t)H * W * 16;
         int js = (int)std::max<size_t>(1, std::min<size_t>((size_t)p.J, slab_bytes / per));
+        if (js < p.J && js >= DEFAULT_TBLOCK)
+            js = js / DEFAULT_TBLOCK * DEFAULT_TBLOCK;
         const int ns = (p.J + js - 1) / js;
-        p.jslab = (p.J + ns - 1) / ns;
+        p.jslab = js;
         p.slabs.assign(ns, Plan::Slab{});
         p.rows.assign(p.perm.begin(), p.perm.end());
         p.jrow.assign(p.J, 0);
@@ -959,11 +964,10 @@ hipError_t enqueue_lambda(Request *q, int s, bool events)
     hipError_t e;
     if (events)
         TRY(hipEventRecord(q->sev[3 * s], st));
+    tno::LambdaArgs las[2];
     for (int o = 0; o < 2; ++o) {
         const auto &L = p.lam[o];
-        if (sl.nj[o] == 0)
-            continue;
-        tno::LambdaArgs la;
+        tno::LambdaArgs &la = las[o];
         la.info = at<tno::TrailInfo>(A, p.o_trail);
         la.colmeta = at<int2>(A, p.o_colmeta);
         la.kvals = at<double>(A, p.o_kvals);
@@ -983,8 +987,8 @@ hipError_t enqueue_lambda(Request *q, int s, bool events)
         la.Pxl = L.Pxl;
         la.Wq = L.Wq;
         la.tr = o;
-        TRY(tno::launch_lambda(st, la));
     }
+    TRY(tno::launch_lambda(st, las[0], las[1]));
     if (events)
         TRY(hipEventRecord(q->sev[3 * s + 1], st));
     return hipSuccess;

@@ -24,7 +24,7 @@ hipError_t launch_table(hipStream_t, int, int, const double *, double, const dou
                         const PrfSpec &, int32_t *, double *) { return hipErrorNotSupported; }
 hipError_t launch_trail(hipStream_t, int, int, int, bool, const int32_t *, const double *, const TrailInfo *,
                         int2 *, double *, int32_t *) { return hipErrorNotSupported; }
-hipError_t launch_lambda(hipStream_t, const LambdaArgs &) { return hipErrorNotSupported; }
+hipError_t launch_lambda(hipStream_t, const LambdaArgs &, const LambdaArgs &) { return hipErrorNotSupported; }
 hipError_t launch_search(hipStream_t, int, bool, int, const SearchArgs &) { return hipErrorNotSupported; }
 hipError_t launch_search_step(hipStream_t, int, bool, int, const SearchArgs &, const StepArgs &, int)
 {
