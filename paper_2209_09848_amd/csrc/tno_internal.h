@@ -162,8 +162,8 @@ hipError_t launch_trail(hipStream_t st, int J, int T, int S, bool sep, const int
                         double *kvals, int32_t *err);
 // Both orientations' normaliser work in one launch (either may have no items).
 hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a0, const LambdaArgs &a1);
-// Variants 0..N_SEARCH_VARIANTS-1 for the separable stamp of side 5; variant 0
-// for every other (stamp, separability).
+// Variants 0..N_SEARCH_VARIANTS-1 for stamps of side 5 (separable or not);
+// variant 0 and the wave-shift variants (sides 1 and 3) for the others.
 hipError_t launch_search(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a);
 // One step of the serving loop over `nblocks` blocks; every request of the
 // step has the stamp, separability, variant and source kind (staged stack, or

@@ -1021,6 +1021,20 @@ static hipError_t launch_search_any(hipStream_t st, int S, bool sep, int variant
         }
         return hipGetLastError();
     }
+    if (S == 5) {   // the general 5 x 5 stamp (tabulated PRF)
+        switch (variant) {
+        case 0: launch_search_t<5, 4, 2, 8, false>(st, a, step, nblocks); break;
+        case 1: launch_search_t<5, 8, 2, 8, false>(st, a, step, nblocks); break;
+        case 2: launch_search_t<5, 2, 2, 8, false>(st, a, step, nblocks); break;
+        case 3: launch_search_t<5, 4, 1, 8, false>(st, a, step, nblocks); break;
+        case 4: launch_search_t<5, 8, 1, 8, false>(st, a, step, nblocks); break;
+        case 5: launch_search_t<5, 4, 4, 8, false>(st, a, step, nblocks); break;
+        case 6: launch_search_t<5, 2, 2, 16, false>(st, a, step, nblocks); break;
+        case 7: launch_search_t<5, 4, 2, 16, false>(st, a, step, nblocks); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (variant != 0)
         return hipErrorInvalidValue;
     if (sep) {
@@ -1038,7 +1052,6 @@ static hipError_t launch_search_any(hipStream_t st, int S, bool sep, int variant
         switch (S) {
         case 1: launch_search_t<1, 4, 2, 8, false>(st, a, step, nblocks); break;
         case 3: launch_search_t<3, 4, 2, 8, false>(st, a, step, nblocks); break;
-        case 5: launch_search_t<5, 4, 2, 8, false>(st, a, step, nblocks); break;
         case 7: launch_search_t<7, 4, 2, 8, false>(st, a, step, nblocks); break;
         case 9: launch_search_t<9, 4, 2, 8, false>(st, a, step, nblocks); break;
         case 11: launch_search_t<11, 4, 2, 8, false>(st, a, step, nblocks); break;

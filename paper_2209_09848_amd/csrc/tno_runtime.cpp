@@ -213,15 +213,15 @@ Fail check_shape(const tno_request *r, const tno_outputs *o)
 constexpr int DEFAULT_TBLOCK = 16;
 
 // Whether search variant v is built for the plan's stamp: variant 0 serves
-// every stamp, the other k_search shapes the separable stamp of side 5, the
-// wave-shift variant stamps 1, 3 and 5 of either kind.
+// every stamp, the other k_search shapes the stamp of side 5 (separable or
+// tabulated), the wave-shift variants stamps 1, 3 and 5 of either kind.
 bool variant_serves(const Plan &p, int v)
 {
     if (v == tno::SEARCH_WS || v == tno::SEARCH_WS4)
         return tno::ws_stamp(p.S);
     if (p.direct)
         return false;
-    return v == 0 || (v > 0 && v < tno::SEARCH_WS && p.S == 5 && p.sep);
+    return v == 0 || (v > 0 && v < tno::SEARCH_WS && p.S == 5);
 }
 
 bool direct_ok(const Plan &p)
@@ -656,10 +656,16 @@ struct ArenaCache {
 
 constexpr int STREAM_POOL = 4;   // at the default priority
 // TNO_CFG_BATCH: step size (blocks), requests per step, step descriptor slots
-constexpr int STEP_BLOCKS = 8192;
+#ifndef TNO_STEP_BLOCKS
+#define TNO_STEP_BLOCKS 8192
+#endif
+#ifndef TNO_STEP_CHUNK_MIN
+#define TNO_STEP_CHUNK_MIN 1024
+#endif
+constexpr int STEP_BLOCKS = TNO_STEP_BLOCKS;
 constexpr int STEP_ENTRIES = 32;
 constexpr int STEP_SLOTS = 4;
-constexpr int STEP_CHUNK_MIN = 1024;   // smallest chunk a request gets in a shared step
+constexpr int STEP_CHUNK_MIN = TNO_STEP_CHUNK_MIN;   // smallest chunk a request gets in a shared step
 
 struct tno_search {
     int device = 0;

@@ -49,6 +49,7 @@ constexpr int SRC_Z = -1;             // staged FP32 stack; otherwise the dtype 
 #endif
 constexpr int WS_AHEAD = TNO_WS_AHEAD;   // window rows read ahead of their use
 
+
 static_assert(WS_TX == SEARCH_VARIANTS[SEARCH_WS].tx && SEARCH_VARIANTS[SEARCH_WS].rpl == 8 &&
               SEARCH_VARIANTS[SEARCH_WS4].tx == WS_TX && SEARCH_VARIANTS[SEARCH_WS4].rpl == 4,
               "variant table out of step");
@@ -264,7 +265,12 @@ __device__ __forceinline__ void search_ws_item(const SearchArgs &a, int item)
 
     // Fetch the window of frame k into registers; returns its column offset d
     // within the first staged group (the window starts at image column
-    // ox = tx0 + ix - 2 and row oy = ty0 + iy - h).
+    // ox = tx0 + ix - 2 and row oy = ty0 + iy - h).  Read in place, ivar is
+    // fetched only when the window covers other pixels than at the previous
+    // fetch (the frame's integer shift moved): otherwise the registers still
+    // hold it (the slots are not written between the store of one window and
+    // the fetch of the next).
+    int f_oy = INT_MIN, f_ox = INT_MIN;
     auto fetch = [&](int k, Raw<SRC> (&pre)[NLD]) -> int {
         k *= a.kstride;
         const cint32_t *e = tabj + (size_t)k * TS;
@@ -311,6 +317,9 @@ __device__ __forceinline__ void search_ws_item(const SearchArgs &a, int item)
             const __amdgpu_buffer_rsrc_t rsc = __builtin_amdgcn_make_buffer_rsrc(
                 (void *)(SRC == TNO_F32 ? a.ivar32 : a.scales + (size_t)k * a.nqy * a.nqx), (short)0,
                 SRC == TNO_F32 ? 0 : a.nqy * a.nqx * 4, BUF_DWORD3);
+            const bool moved = oy != f_oy || ox != f_ox;   // wave-uniform
+            f_oy = oy;
+            f_ox = ox;
 #pragma unroll
             for (int it = 0; it < NLD; ++it) {
                 int r, g;
@@ -320,7 +329,8 @@ __device__ __forceinline__ void search_ws_item(const SearchArgs &a, int item)
                                 (inside || ((unsigned)y < (unsigned)a.H && (unsigned)gi < (unsigned)W4));
                 const uint32_t eo = inside ? soff[it] : (uint32_t)(y * a.W + 4 * gi);
                 const int ro = (int)(ok ? eo * (uint32_t)EB : OOB), io = (int)(ok ? eo * 4u : OOB);
-                pre[it].iv = as_f4(__builtin_amdgcn_raw_buffer_load_b128(ri, io, 0, 0));
+                if (moved)
+                    pre[it].iv = as_f4(__builtin_amdgcn_raw_buffer_load_b128(ri, io, 0, 0));
                 if constexpr (SRC == TNO_F32) {
                     pre[it].r = as_f4(__builtin_amdgcn_raw_buffer_load_b128(rr, ro, 0, 0));
                 } else {

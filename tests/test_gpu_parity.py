@@ -505,6 +505,41 @@ def test_every_tile_shape_and_block_gives_identical_bits(tmp_path):
             assert np.array_equal(g["best_traj"], ref["best_traj"])
 
 
+def test_tabulated_stamp_tile_shapes_give_identical_bits(tmp_path):
+    """The general 5 x 5 stamp (tabulated PRF, jitter) in every k_search tile
+    shape and two trajectory blocks: the bits of the first shape, which
+    matches the oracle."""
+    R, sigma, times, vel = _rand_problem(83, 13, 75, 290, 5)
+    T, H, W = R.shape
+    J = vel.shape[0]
+    q = 4
+    tab = synth.TabulatedPSF().table(5, q)
+    jit = synth.jitter_series(synth.rng(83, 9), T, amp=0.3)
+    kw = dict(prf_kind=tno.TNO_PRF_TABLE, prf_table=_to(tab), prf_q=q, jitter=_to(jit))
+    o = oracle.search(R, sigma, times, float(times[0]), vel, prf_kind=oracle.PRF_TABLE, prf_table=tab,
+                      prf_q=q, jitter=jit)
+    ref = None
+    for name in tno.SEARCH_VARIANTS:
+        if name.startswith("ws"):
+            continue
+        for tb in (J, 2):
+            print("tabulated variant", name, "tblock", tb, flush=True)
+            path = tmp_path / ("tune_p_%s_%d.txt" % (name, tb))
+            path.write_text("%s %s %s %d 1.0\n" % (_arch(), tno.shape_class(H, W, T, J, tabulated=True), name, tb))
+            with tno.Search(0, tune_cache_path=str(path)) as h:
+                g, res = tno.search_tensors(_to(R), _to(sigma), _to(times), _to(vel), t_ref=float(times[0]),
+                                            top_k=20, handle=h, **kw)
+            torch.cuda.synchronize()
+            assert res.status == 0, res.message
+            snr, flux = g["snr"].cpu().numpy(), g["flux"].cpu().numpy()
+            if ref is None:
+                parity.check_maps(snr, flux, o)
+                ref = (snr, flux, tno.decode_candidates(g["topk"], res.n_topk))
+                continue
+            assert np.array_equal(snr, ref[0]) and np.array_equal(flux, ref[1])
+            assert tno.decode_candidates(g["topk"], res.n_topk) == ref[2]
+
+
 @pytest.mark.parametrize("variant", ["ws", "ws4"])
 @pytest.mark.parametrize("stamp,kind", [(1, 0), (3, 0), (5, 0), (5, 1), (3, "table"), (5, "table")])
 def test_wave_shift_variant_stamps_and_edges(tmp_path, stamp, kind, variant):
