@@ -373,8 +373,9 @@ uint64_t tno_search_footprint(const tno_request *req, const tno_outputs *out);
  * of tno_search_submit + tno_search_poll as one synchronous call on `stream`
  * (hipStream_t, NULL = the default stream) of the current device, with every
  * intermediate buffer (staged stack, ivar maps, offset/weight table, trail
- * kernels, normaliser, SNR/flux maps the caller does not take, tile keys,
- * top-k state) placed in a fixed TNO_SCRATCH_BYTES array that the library's
+ * kernels, normaliser and SNR/flux maps of a trajectory slab, tile keys,
+ * top-k state; slabs here hold at most TNO_SCRATCH_BYTES / 4 bytes, so a
+ * large bank runs in more slabs) placed in a fixed TNO_SCRATCH_BYTES array that the library's
  * code object holds on each GPU it runs on, until the process ends.  No
  * handle, no hipMalloc/hipFree and no allocating library call; the small
  * inputs the plan needs (times, velocities, jitter) are read back to host
@@ -385,8 +386,8 @@ uint64_t tno_search_footprint(const tno_request *req, const tno_outputs *out);
  *             per-phase times are 0).
  * Returns TNO_OK; TNO_E_INVAL for an invalid request (as tno_search_validate)
  * or without TNO_REQ_DEVICE_PTRS / with a stack_key; TNO_E_NOMEM when the
- * request's working memory (tno_search_footprint minus the caller's buffers)
- * exceeds TNO_SCRATCH_BYTES; TNO_E_DEVICE on a HIP error.  Calls on one GPU
+ * request's working memory (with those slabs) exceeds TNO_SCRATCH_BYTES;
+ * TNO_E_DEVICE on a HIP error.  Calls on one GPU
  * share its array: the library serialises the calls of one process on a GPU
  * (a lock held for the whole call), and every buffer a search needs cleared is
  * cleared by its kernels; calls from several processes each hold their own

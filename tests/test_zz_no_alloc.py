@@ -3,7 +3,9 @@ memory is the library's fixed per-GPU array) against the ticketed search
 (tno_search_submit / poll) on the same inputs: identical bits, on two calls in
 a row (the second smaller, so it runs over what the first left in the array)
 and one reduced-precision call whose maps stay inside the array; a request
-whose working memory exceeds the array is refused."""
+whose normaliser and maps for all trajectories exceed the array runs in
+trajectory slabs; a request whose working memory exceeds the array is
+refused."""
 import numpy as np
 import pytest
 import torch
@@ -78,6 +80,24 @@ def test_scratch_search_matches_ticketed_search():
                             None) == 0
     torch.cuda.synchronize()
     _compare(codes, sigma, times, vel, k=9, maps=False, dtype="bf16", scales=scales)
+
+
+def test_scratch_search_in_trajectory_slabs():
+    """A request whose normaliser and maps for all trajectories exceed the
+    array runs in trajectory slabs of a quarter of it (here 3 slabs of at
+    most 8 of 20 trajectories), with the bits of the ticketed search (one
+    slab)."""
+    print("scratch search: BF16 in place, 512 x 512 x 24 frames, 20 trajectories in slabs", flush=True)
+    R, sigma, times, vel = _problem(4, 24, 512, 512, 20)
+    T, H, W = R.shape
+    Rt = _to(R)
+    codes = torch.empty((T, H, W), dtype=torch.int16, device=DEV)
+    scales = torch.empty((T, (H + 63) // 64, (W + 63) // 64), dtype=torch.float32, device=DEV)
+    assert tno.tno_quantize(T, H, W, tno.TNO_BF16, Rt.data_ptr(), codes.data_ptr(), scales.data_ptr(),
+                            None) == 0
+    torch.cuda.synchronize()
+    assert 20 * H * W * 16 > tno.TNO_SCRATCH_BYTES // 4
+    _compare(codes, sigma, times, vel, k=40, maps=False, dtype="bf16", scales=scales)
 
 
 def test_scratch_search_refuses_what_does_not_fit():
