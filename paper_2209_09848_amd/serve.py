@@ -118,7 +118,7 @@ class StackPool:
 
 def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=16,
                max_inflight=8, log=None, mode="eager", keep=False, stats=None, slab_bytes=0,
-               stage_fp32=False):
+               stage_fp32=False, on_poll=None):
     """Serve `specs` in arrival order; mode "eager" (each request's kernels on
     a pool stream), "graphs" (each request as a HIP graph) or "batch" (the
     searches of admitted requests share steps).  Returns per-request records
@@ -126,7 +126,8 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
     `stats` dict receives the handle's statistics at the end; slab_bytes: the
     handle's trajectory slab size (0: the library's default); stage_fp32: a
     reduced-precision stack is decoded into an FP32 copy per request
-    (TNO_REQ_STAGE_FP32) instead of searched in place."""
+    (TNO_REQ_STAGE_FP32) instead of searched in place; on_poll(handle) is
+    called after every round of polls."""
     import torch
     pool = StackPool({s.key: (s.side, s.frames) for s in specs}, dtype, device)
     vel_all = torch.from_numpy(bank).to(device)
@@ -201,6 +202,8 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
                         (s.key, s.side, s.side, s.frames, len(s.traj_idx), recs[-1]["latency_ms"]))
             for t in done:
                 del inflight[t]
+            if on_poll is not None:
+                on_poll(h)
             if not done:
                 time.sleep(0.0005)
         if stats is not None:

@@ -69,3 +69,29 @@ def test_stream_results_equal_alone(mode, slab_bytes):
             parity.check_traj_max(peaks, ora["snr"], ora["flux"])
             checked += 1
     print("20 requests equal alone; %d checked against the oracle" % checked, flush=True)
+
+
+def test_admission_accounts_the_blocks_it_holds():
+    """Uneven requests under a tight HBM budget (requests wait for room):
+    at every round of polls the bytes the handle counts as in use equal the
+    device blocks that live requests and resident stacks hold, and in-use
+    plus cached bytes stay within the budget."""
+    bank, _ = synth.grid_shells()
+    shapes = serve.draw_stack_shapes(4, seed=11, sides=[256, 384, 512], frames=(60, 160))
+    specs = serve.draw_requests(16, shapes, bank.shape[0], seed=11, jrange=(8, 48))
+    specs = serve.poisson_arrivals(specs, rate=1000.0, seed=11)
+    seen = {"polls": 0, "max_in_use": 0}
+
+    def check(h):
+        st = tno.tno_search_stats(h.h)
+        assert st.in_use_bytes == st.held_bytes, (st.in_use_bytes, st.held_bytes)
+        assert st.in_use_bytes + st.cached_bytes <= st.budget_bytes
+        seen["polls"] += 1
+        seen["max_in_use"] = max(seen["max_in_use"], st.in_use_bytes)
+
+    budget_gb = 0.6
+    recs = serve.run_stream(specs, bank, dtype="bf16", budget_gb=budget_gb, max_inflight=8, top_k=K,
+                            on_poll=check)
+    assert len(recs) == 16 and seen["polls"] > 0
+    print("polls %d, most bytes in use %.3g GB of %.3g" % (seen["polls"], seen["max_in_use"] / 1e9, budget_gb),
+          flush=True)
