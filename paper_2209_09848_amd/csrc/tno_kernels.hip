@@ -535,7 +535,11 @@ hipError_t launch_lambda(hipStream_t st, const LambdaArgs &a0, const LambdaArgs 
 // per frame.  The table entry (shift, weights) is wave-uniform (scalar loads).
 // Frame partials accumulate in FP32 over FRAME_CHUNK frames, then into FP64;
 // every form adds the terms of an output in the same order.
-template <int S, int NWAVE, int CPL, int RPL, bool SEP, bool XCH>
+// SRC: the window's source, the staged stack Z (SRC_Z) or a reduced-precision
+// stack read in place (its dtype): codes, tile scale and ivar are fetched and
+// decode x scale x ivar is stored, the very products the staging of Z forms,
+// so both sources give the same bits.
+template <int S, int NWAVE, int CPL, int RPL, bool SEP, bool XCH, int SRC = SRC_Z>
 __device__ __forceinline__ void search_item(const SearchArgs &a, int item)
 {
     constexpr int h = S / 2;
@@ -572,14 +576,18 @@ __device__ __forceinline__ void search_item(const SearchArgs &a, int item)
     const int lane = tid & 63, wv = tid >> 6;
 
     // This thread's staging slots: window group idx = tid + NT*it at (row r,
-    // group g), byte offset (r * Wp4 + g) * 16 from the window origin (below
-    // 2^32: WY * Wp4 * 16 is).
+    // group g): Z's byte offset (r * Wp4 + g) * 16 from the window origin
+    // (below 2^32: WY * Wp4 * 16 is); read in place, the element offset
+    // r * W + 4g (every pixel offset fits: H * W * 4 < 2^31)
     uint32_t soff[NLD];
 #pragma unroll
     for (int it = 0; it < NLD; ++it) {
         const int idx = tid + NT * it;
         const int r = idx / NG;
-        soff[it] = (uint32_t)(r * a.Wp4 + (idx - r * NG)) * 16u;
+        if constexpr (SRC == SRC_Z)
+            soff[it] = (uint32_t)(r * a.Wp4 + (idx - r * NG)) * 16u;
+        else
+            soff[it] = (uint32_t)(r * a.W + 4 * (idx - r * NG));
     }
     // only the last slot can fall past the window; such a lane's buffer
     // offset is set past every resource, so it reads 0 and touches no memory
@@ -593,40 +601,87 @@ __device__ __forceinline__ void search_item(const SearchArgs &a, int item)
     const size_t frame4 = (size_t)a.Hp * a.Wp4;
 
     // Fetch the window of frame k into registers; returns its sub-float4 offset.
-    auto fetch = [&](int k, float4 (&pre)[NLD]) -> int {
+    // Read in place, ivar is fetched only when the window covers other pixels
+    // than at the previous fetch (the slots are not written between the store
+    // of one window and the fetch of the next, so they still hold it).
+    int f_oy = INT_MIN, f_ox = INT_MIN;
+    auto fetch = [&](int k, Raw<SRC> (&pre)[NLD]) -> int {
         k *= a.kstride;
         const cint32_t *e = tabj + (size_t)k * TS;
-        const int oy = ty0 + e[0] - h + a.Pt;
-        const int ox = tx0 + e[1] - h + a.Pl;
-        const int ag = ox >> 2;      // floor division (arithmetic shift)
-        const float4 *Zk = a.Z4 + (size_t)k * frame4;
-        if (oy >= 0 && oy + WY <= a.Hp && ag >= 0 && ag + NG <= a.Wp4) {
-            // buffer loads from a resource at the window origin (scalar
-            // registers) plus 32-bit lane offsets; the resource ends with the
-            // frame (at most 2^31 - 1 bytes on), so no load reaches past it
-            const size_t o0 = (size_t)oy * a.Wp4 + ag;
-            const size_t rem = (frame4 - o0) * 16;
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void *)(Zk + o0), (short)0, (int)(rem < 0x7FFFFFFFu ? rem : 0x7FFFFFFFu), BUF_DWORD3);
-#pragma unroll
-            for (int it = 0; it < NLD; ++it) {
-                const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)soff[it], 0, 0);
-                pre[it] = make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]),
-                                      __uint_as_float(v[2]), __uint_as_float(v[3]));
-            }
-        } else {
+        if constexpr (SRC != SRC_Z) {
+            constexpr int EB = src_bytes<SRC>();
+            constexpr uint32_t OOB = 0x80000000u;
+            const size_t HW = (size_t)a.H * a.W;
+            const int W4 = a.W >> 2;
+            const int oy = ty0 + e[0] - h;
+            const int ox = tx0 + e[1] - h;
+            const int ag = ox >> 2;   // floor
+            const bool inside = oy >= 0 && oy + WY <= a.H && ag >= 0 && ag + NG <= W4;
+            // resources at the window origin (inside the image) or at the
+            // frame start; OOB lies past every resource
+            const size_t e0 = inside ? (size_t)oy * a.W + 4 * (size_t)ag : 0;
+            const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)((const char *)a.R + ((size_t)k * HW + e0) * EB), (short)0, (int)((HW - e0) * EB),
+                BUF_DWORD3);
+            const __amdgpu_buffer_rsrc_t ri = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(a.ivar32 + e0), (short)0, (int)((HW - e0) * 4), BUF_DWORD3);
+            const __amdgpu_buffer_rsrc_t rsc = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(a.scales + (size_t)k * a.nqy * a.nqx), (short)0, a.nqy * a.nqx * 4, BUF_DWORD3);
+            const bool moved = oy != f_oy || ox != f_ox;   // wave-uniform
+            f_oy = oy;
+            f_ox = ox;
 #pragma unroll
             for (int it = 0; it < NLD; ++it) {
                 const int idx = tid + NT * it;
-                const int r = idx / NG;
-                const int yp = oy + r, gp = ag + (idx - r * NG);
-                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (idx < NWIN && (unsigned)yp < (unsigned)a.Hp && (unsigned)gp < (unsigned)a.Wp4)
-                    v = Zk[(size_t)yp * a.Wp4 + gp];
-                pre[it] = v;
+                const int r = idx / NG, g = idx - r * NG;
+                const int y = oy + r, gi = ag + g;
+                const bool ok = (it < NLD - 1 || last_ok) &&
+                                (inside || ((unsigned)y < (unsigned)a.H && (unsigned)gi < (unsigned)W4));
+                const uint32_t eo = inside ? soff[it] : (uint32_t)(y * a.W + 4 * gi);
+                const int ro = (int)(ok ? eo * (uint32_t)EB : OOB), io = (int)(ok ? eo * 4u : OOB);
+                if (moved)
+                    pre[it].iv = as_f4(__builtin_amdgcn_raw_buffer_load_b128(ri, io, 0, 0));
+                if constexpr (SRC == TNO_FP8_E4M3) {
+                    pre[it].c = __builtin_amdgcn_raw_buffer_load_b32(rr, ro, 0, 0);
+                } else {
+                    const auto c = __builtin_amdgcn_raw_buffer_load_b64(rr, ro, 0, 0);
+                    pre[it].c = make_uint2(c[0], c[1]);
+                }
+                // the frame's scale of the 64 x 64 tile holding (y, 4gi)
+                const int so = (int)(ok ? (uint32_t)(((y >> 6) * a.nqx + (gi >> 4)) * 4) : OOB);
+                pre[it].s = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsc, so, 0, 0));
             }
+            return ox & 3;
+        } else {
+            const int oy = ty0 + e[0] - h + a.Pt;
+            const int ox = tx0 + e[1] - h + a.Pl;
+            const int ag = ox >> 2;      // floor division (arithmetic shift)
+            const float4 *Zk = a.Z4 + (size_t)k * frame4;
+            if (oy >= 0 && oy + WY <= a.Hp && ag >= 0 && ag + NG <= a.Wp4) {
+                // buffer loads from a resource at the window origin (scalar
+                // registers) plus 32-bit lane offsets; the resource ends with the
+                // frame (at most 2^31 - 1 bytes on), so no load reaches past it
+                const size_t o0 = (size_t)oy * a.Wp4 + ag;
+                const size_t rem = (frame4 - o0) * 16;
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)(Zk + o0), (short)0, (int)(rem < 0x7FFFFFFFu ? rem : 0x7FFFFFFFu), BUF_DWORD3);
+#pragma unroll
+                for (int it = 0; it < NLD; ++it)
+                    pre[it].z = as_f4(__builtin_amdgcn_raw_buffer_load_b128(rs, (int)soff[it], 0, 0));
+            } else {
+#pragma unroll
+                for (int it = 0; it < NLD; ++it) {
+                    const int idx = tid + NT * it;
+                    const int r = idx / NG;
+                    const int yp = oy + r, gp = ag + (idx - r * NG);
+                    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if (idx < NWIN && (unsigned)yp < (unsigned)a.Hp && (unsigned)gp < (unsigned)a.Wp4)
+                        v = Zk[(size_t)yp * a.Wp4 + gp];
+                    pre[it].z = v;
+                }
+            }
+            return ox - (ag << 2);
         }
-        return ox - (ag << 2);
     };
     // LDS window, de-interleaved: the even columns of all WY rows, then the
     // odd columns (rows of LH floats each).  A staged group arrives as (even,
@@ -638,14 +693,23 @@ __device__ __forceinline__ void search_item(const SearchArgs &a, int item)
     constexpr bool SPLIT = CPL % 2 == 0;
     constexpr int LH = LS / 2;
     constexpr int HALF = WY * LH;
-    auto store = [&](int buf, const float4 (&pre)[NLD]) {
+    auto store = [&](int buf, const Raw<SRC> (&pre)[NLD]) {
 #pragma unroll
         for (int it = 0; it < NLD; ++it)
             if (it < NLD - 1 || last_ok) {
                 const int idx = tid + NT * it;
                 const int r = idx / NG, g = idx - r * NG;
-                reinterpret_cast<float2 *>(&win[buf][r * LH])[g] = make_float2(pre[it].x, pre[it].y);
-                reinterpret_cast<float2 *>(&win[buf][HALF + r * LH])[g] = make_float2(pre[it].z, pre[it].w);
+                float2 ev, od;
+                if constexpr (SRC == SRC_Z) {
+                    ev = make_float2(pre[it].z.x, pre[it].z.y);
+                    od = make_float2(pre[it].z.z, pre[it].z.w);
+                } else {
+                    const float4 v = decode_group<SRC>(pre[it]);   // image column order
+                    ev = make_float2(v.x, v.z);
+                    od = make_float2(v.y, v.w);
+                }
+                reinterpret_cast<float2 *>(&win[buf][r * LH])[g] = ev;
+                reinterpret_cast<float2 *>(&win[buf][HALF + r * LH])[g] = od;
             }
     };
 
@@ -690,7 +754,7 @@ __device__ __forceinline__ void search_item(const SearchArgs &a, int item)
         }
     };
 
-    float4 pre[NLD];
+    Raw<SRC> pre[NLD];
     int d_cur = fetch(0, pre);
     store(0, pre);
     __syncthreads();
@@ -962,25 +1026,29 @@ __device__ __forceinline__ void search_item(const SearchArgs &a, int item)
 }
 
 // One request: block b takes work item xcd_item(b) of the request.
-template <int S, int NWAVE, int CPL, int RPL, bool SEP, bool XCH>
-__global__ __launch_bounds__(64 * NWAVE) void k_search(SearchArgs a)
+// (4 waves per SIMD: a stack read in place holds more registers per staged
+// group, and the allocation is held at 128 VGPRs rather than lose a wave.)
+template <int S, int NWAVE, int CPL, int RPL, bool SEP, bool XCH, int SRC>
+__global__ __launch_bounds__(64 * NWAVE) __attribute__((amdgpu_waves_per_eu(SRC == SRC_Z ? 1 : 4)))
+void k_search(SearchArgs a)
 {
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item < a.n_items)
-        search_item<S, NWAVE, CPL, RPL, SEP, XCH>(a, item);
+        search_item<S, NWAVE, CPL, RPL, SEP, XCH, SRC>(a, item);
 }
 
 // A step of the serving loop: consecutive block ranges take work items of
 // different requests (step_item maps a block to its request and item).
-template <int S, int NWAVE, int CPL, int RPL, bool SEP, bool XCH>
-__global__ __launch_bounds__(64 * NWAVE) void k_search_step(StepArgs s)
+template <int S, int NWAVE, int CPL, int RPL, bool SEP, bool XCH, int SRC>
+__global__ __launch_bounds__(64 * NWAVE) __attribute__((amdgpu_waves_per_eu(SRC == SRC_Z ? 1 : 4)))
+void k_search_step(StepArgs s)
 {
     int r, item;
     if (step_item(s, r, item))
-        search_item<S, NWAVE, CPL, RPL, SEP, XCH>(step_args(s, r), item);
+        search_item<S, NWAVE, CPL, RPL, SEP, XCH, SRC>(step_args(s, r), item);
 }
 
-template <int S, int NWAVE, int CPL, int RPL = 8, bool SEP = true>
+template <int S, int NWAVE, int CPL, int RPL = 8, bool SEP = true, int SRC = SRC_Z>
 static void launch_search_t(hipStream_t st, const SearchArgs &a, const StepArgs *step = nullptr,
                             int nblocks = 0)
 {
@@ -993,11 +1061,25 @@ static void launch_search_t(hipStream_t st, const SearchArgs &a, const StepArgs 
     constexpr bool XCH = SEP && CPL % 2 == 0 && S > 1 && S - 1 <= RPL && NWAVE > 1 && NWAVE <= 4 &&
                          LDS_PER_CU / LDS_X >= LDS_PER_CU / LDS_2;
     if (step)
-        hipLaunchKernelGGL((k_search_step<S, NWAVE, CPL, RPL, SEP, XCH>), dim3(nblocks), dim3(64 * NWAVE), 0, st,
-                           *step);
+        hipLaunchKernelGGL((k_search_step<S, NWAVE, CPL, RPL, SEP, XCH, SRC>), dim3(nblocks), dim3(64 * NWAVE), 0,
+                           st, *step);
     else
-        hipLaunchKernelGGL((k_search<S, NWAVE, CPL, RPL, SEP, XCH>), dim3(xcd_grid(a.n_items)),
+        hipLaunchKernelGGL((k_search<S, NWAVE, CPL, RPL, SEP, XCH, SRC>), dim3(xcd_grid(a.n_items)),
                            dim3(64 * NWAVE), 0, st, a);
+}
+
+// The default tile shape for a stack of `dtype` read in place (stamp 5).
+template <bool SEP>
+static hipError_t launch_search_direct(hipStream_t st, int dtype, const SearchArgs &a, const StepArgs *step,
+                                       int nblocks)
+{
+    switch (dtype) {
+    case TNO_BF16: launch_search_t<5, 4, 2, 8, SEP, TNO_BF16>(st, a, step, nblocks); break;
+    case TNO_F16: launch_search_t<5, 4, 2, 8, SEP, TNO_F16>(st, a, step, nblocks); break;
+    case TNO_FP8_E4M3: launch_search_t<5, 4, 2, 8, SEP, TNO_FP8_E4M3>(st, a, step, nblocks); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 static hipError_t launch_search_any(hipStream_t st, int S, bool sep, int variant, const SearchArgs &a,
@@ -1005,8 +1087,13 @@ static hipError_t launch_search_any(hipStream_t st, int S, bool sep, int variant
 {
     if (variant == SEARCH_WS || variant == SEARCH_WS4)
         return ws_stamp(S) ? launch_search_ws(st, S, sep, variant, a, step, nblocks) : hipErrorInvalidValue;
-    if (!a.Z4)
-        return hipErrorInvalidValue;   // k_search reads the staged stack only
+    if (!a.Z4) {
+        // a reduced-precision stack read in place: the default shape, stamp 5
+        if (variant != 0 || S != 5)
+            return hipErrorInvalidValue;
+        return sep ? launch_search_direct<true>(st, a.dtype, a, step, nblocks)
+                   : launch_search_direct<false>(st, a.dtype, a, step, nblocks);
+    }
     if (S == 5 && sep) {
         switch (variant) {
         case 0: launch_search_t<5, 4, 2>(st, a, step, nblocks); break;

@@ -214,19 +214,27 @@ constexpr int DEFAULT_TBLOCK = 16;
 
 // Whether search variant v is built for the plan's stamp: variant 0 serves
 // every stamp, the other k_search shapes the stamp of side 5 (separable or
-// tabulated), the wave-shift variants stamps 1, 3 and 5 of either kind.
+// tabulated), the wave-shift variants stamps 1, 3 and 5 of either kind; a
+// stack read in place: the wave-shift variants, and variant 0 for stamp 5.
 bool variant_serves(const Plan &p, int v)
 {
     if (v == tno::SEARCH_WS || v == tno::SEARCH_WS4)
         return tno::ws_stamp(p.S);
     if (p.direct)
-        return false;
+        return v == 0 && p.S == 5;   // the default k_search shape reads stamp-5 stacks in place
     return v == 0 || (v > 0 && v < tno::SEARCH_WS && p.S == 5);
 }
 
 bool direct_ok(const Plan &p)
 {
     return tno::ws_stamp(p.S) && p.W % 4 == 0 && (double)p.H * p.W * 4.0 < 2147483647.0;
+}
+
+int default_variant(const Plan &p)
+{
+    if (!p.direct)
+        return 0;
+    return p.dtype == TNO_FP8_E4M3 && p.S == 5 ? 0 : tno::SEARCH_WS;
 }
 
 void set_search_shape(Plan &p, int v, int tblock)
@@ -354,12 +362,14 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     // the wave-shift search serves the stamp, unless the caller asks for the
     // staged copy
     p.direct = p.dtype != TNO_F32 && (r->flags & TNO_REQ_STAGE_FP32) == 0 && direct_ok(p);
-    // untuned default: the first tile shape (the wave-shift shape for a
-    // direct search), trajectories in blocks of 16 (on the 100-trajectory FFI
-    // bank 2.7 % faster than one block of all, and blocks of 8 are 25 %
+    // untuned default: the first tile shape (for a stack read in place the
+    // wave-shift shape, except FP8 codes with stamp 5, which the first shape
+    // reads faster: on the FFI workload 238 against 272 ms, where BF16 takes
+    // 261 against 255), trajectories in blocks of 16 (on the 100-trajectory
+    // FFI bank 2.7 % faster than one block of all, and blocks of 8 are 25 %
     // slower: fewer trajectories of a tile run together and share its windows
     // in L2)
-    set_search_shape(p, p.direct ? tno::SEARCH_WS : 0, DEFAULT_TBLOCK);
+    set_search_shape(p, default_variant(p), DEFAULT_TBLOCK);
     p.ntiles_max = ((W + 63) / 64) * ((H + 15) / 16);
     // search order: trajectories adjacent in the work order should have nearby
     // shifts, so that the windows of a tile's co-resident blocks share cache
@@ -666,6 +676,7 @@ constexpr int STEP_BLOCKS = TNO_STEP_BLOCKS;
 constexpr int STEP_ENTRIES = 32;
 constexpr int STEP_SLOTS = 4;
 constexpr int STEP_CHUNK_MIN = TNO_STEP_CHUNK_MIN;   // smallest chunk a request gets in a shared step
+constexpr int STEP_OLDEST_QUARTERS = 2;               // quarters of a shared step for the oldest request
 
 struct tno_search {
     int device = 0;
@@ -1164,7 +1175,7 @@ hipError_t autotune(tno_search *h, Request *q)
     // candidate's probe beats it by more than 2 %: a short probe does not
     // rank candidates that close reliably over the whole sequence
     int def = 0;
-    const int def_v = p.direct ? tno::SEARCH_WS : 0;
+    const int def_v = default_variant(p);
     for (size_t i = 0; i < cands.size(); ++i)
         if (cands[i].v == def_v && cands[i].tb == std::min(DEFAULT_TBLOCK, p.J))
             def = (int)i;
@@ -1310,7 +1321,14 @@ hipError_t pump(tno_search *h)
         }
         if (take.empty())
             return hipSuccess;
-        const int share = std::max(STEP_CHUNK_MIN, (STEP_BLOCKS / (int)take.size() + 7) / 8 * 8);
+        // the oldest request takes half of the step and the rest share the
+        // other half (equal shares throughout slowed the largest requests:
+        // p99 ≈ 325 against ≈ 280 ms on the serving mix of the bench)
+        constexpr int OQ = STEP_OLDEST_QUARTERS;
+        const int nt = (int)take.size();
+        const int share = OQ && nt > 1 ? std::max(STEP_CHUNK_MIN, (STEP_BLOCKS * (4 - OQ) / 4 / (nt - 1) + 7) / 8 * 8)
+                                       : std::max(STEP_CHUNK_MIN, (STEP_BLOCKS / nt + 7) / 8 * 8);
+        const int share0 = OQ && nt > 1 ? STEP_BLOCKS * OQ / 4 : share;
         auto &sl = h->slots[slot];
         tno::SearchArgs *args = (tno::SearchArgs *)sl.host;
         tno::StepEntry *ent = (tno::StepEntry *)((char *)sl.host + STEP_ENTRIES * sizeof(tno::SearchArgs));
@@ -1318,7 +1336,7 @@ hipError_t pump(tno_search *h)
         for (Request *q : take) {
             const Plan &p = q->plan;
             const int n_items = p.ntiles * (p.slabs[q->slab].a1 - p.slabs[q->slab].a0);
-            const int cnt = std::min(share, n_items - q->next_item);
+            const int cnt = std::min(n == 0 ? share0 : share, n_items - q->next_item);
             args[n] = search_args(q, q->slab, p.T);
             ent[n] = {nblocks, (cnt + 7) / 8 * 8, q->next_item, cnt};
             nblocks += ent[n].nblk;

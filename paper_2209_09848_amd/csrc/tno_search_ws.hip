@@ -43,7 +43,6 @@ constexpr int WS_NWAVE = 4;
 constexpr int WS_TX = 124;            // start columns per tile (lanes 1..62, two each)
 constexpr int WS_NG = 33;             // staged float4 groups per row: offset 0..3 + 128 columns
 constexpr int WS_LS = 136;            // LDS floats per window row (a multiple of 4)
-constexpr int SRC_Z = -1;             // staged FP32 stack; otherwise the dtype read directly
 #ifndef TNO_WS_AHEAD
 #define TNO_WS_AHEAD 1
 #endif
@@ -115,78 +114,6 @@ __device__ __forceinline__ void horiz_ws<1>(float ve, float vo, const float (&)[
 {
     h0 = ve;
     h1 = vo;
-}
-
-// One staged group (4 image columns) as loaded, before decoding.
-template <int SRC>
-struct Raw {
-    float4 z;                  // SRC_Z: the staged values
-};
-template <>
-struct Raw<TNO_F32> {
-    float4 r, iv;
-};
-template <>
-struct Raw<TNO_BF16> {
-    uint2 c;
-    float4 iv;
-    float s;
-};
-template <>
-struct Raw<TNO_F16> {
-    uint2 c;
-    float4 iv;
-    float s;
-};
-template <>
-struct Raw<TNO_FP8_E4M3> {
-    uint32_t c;
-    float4 iv;
-    float s;
-};
-
-template <int SRC>
-constexpr int src_bytes() { return SRC == SRC_Z || SRC == TNO_F32 ? 4 : SRC == TNO_FP8_E4M3 ? 1 : 2; }
-
-template <class V>
-__device__ __forceinline__ float4 as_f4(const V &v)
-{
-    return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3]));
-}
-
-// Decode a staged group into image column order: Z reordered; otherwise
-// (code * scale) * ivar per column, rounded as the staging of Z rounds them.
-template <int SRC>
-__device__ __forceinline__ float4 decode_group(const Raw<SRC> &g)
-{
-    if constexpr (SRC == SRC_Z) {
-        return make_float4(g.z.x, g.z.z, g.z.y, g.z.w);   // Z holds 4g, 4g+2, 4g+1, 4g+3
-    } else if constexpr (SRC == TNO_F32) {
-        return make_float4(g.r.x * g.iv.x, g.r.y * g.iv.y, g.r.z * g.iv.z, g.r.w * g.iv.w);
-    } else {
-        float r[4];
-        if constexpr (SRC == TNO_BF16) {
-            r[0] = __uint_as_float(g.c.x << 16) * g.s;
-            r[1] = __uint_as_float(g.c.x & 0xFFFF0000u) * g.s;
-            r[2] = __uint_as_float(g.c.y << 16) * g.s;
-            r[3] = __uint_as_float(g.c.y & 0xFFFF0000u) * g.s;
-        } else if constexpr (SRC == TNO_F16) {
-            const uint32_t c[4] = {g.c.x & 0xFFFFu, g.c.x >> 16, g.c.y & 0xFFFFu, g.c.y >> 16};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint16_t hb = (uint16_t)c[e];
-                _Float16 hv;
-                __builtin_memcpy(&hv, &hb, 2);
-                r[e] = (float)hv * g.s;
-            }
-        } else {
-            const float s8 = g.s * 256.0f;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                r[e] = decode_e4m3((g.c >> (8 * e)) & 0xFFu) * s8;
-        }
-        return make_float4(r[0] * g.iv.x, r[1] * g.iv.y, r[2] * g.iv.z, r[3] * g.iv.w);
-    }
 }
 
 }  // namespace

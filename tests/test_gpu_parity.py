@@ -540,6 +540,52 @@ def test_tabulated_stamp_tile_shapes_give_identical_bits(tmp_path):
             assert tno.decode_candidates(g["topk"], res.n_topk) == ref[2]
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "f16", "fp8_e4m3"])
+@pytest.mark.parametrize("kind", [0, "table"])
+def test_in_place_k_search_gives_the_bits_of_the_staged_stack(tmp_path, dtype, kind):
+    """k_search reading a reduced-precision stack in place stores decode x
+    scale x ivar into its window -- the products the staging of Z forms -- so
+    it must give the bits of the same shape searching the staged copy
+    (TNO_REQ_STAGE_FP32), on a ragged image wider than a tile with trails
+    leaving the frame; and match the oracle on the dequantized values."""
+    R, sigma, times, vel = _rand_problem(940 + (kind == "table"), 17, 70, 388, 4)
+    vel = vel * 3.0
+    T, H, W = R.shape
+    J = vel.shape[0]
+    codes = torch.empty((T, H, W), device=DEV, dtype=torch.uint8 if dtype == "fp8_e4m3" else torch.int16)
+    sc = torch.empty((T, (H + 63) // 64, (W + 63) // 64), device=DEV)
+    Rt = _to(R)
+    assert tno.tno_quantize(T, H, W, tno.DTYPE_CODE[dtype], Rt.data_ptr(), codes.data_ptr(), sc.data_ptr(),
+                            None) == 0
+    torch.cuda.synchronize()
+    kw = dict(dtype=dtype, scales=sc, top_k=15)
+    okw = {}
+    if kind == "table":
+        q = 4
+        tab = synth.TabulatedPSF().table(5, q)
+        kw.update(prf_kind=tno.TNO_PRF_TABLE, prf_table=_to(tab), prf_q=q)
+        okw = dict(prf_kind=oracle.PRF_TABLE, prf_table=tab, prf_q=q)
+    got = {}
+    for stage in (False, True):
+        cls = tno.shape_class(H, W, T, J, tabulated=kind == "table", direct=not stage)
+        path = tmp_path / ("tune_%s_%d.txt" % (dtype, stage))
+        path.write_text("%s %s w4c2 %d 1.0\n" % (_arch(), cls, J))
+        flags = tno.TNO_REQ_DEVICE_PTRS | (tno.TNO_REQ_STAGE_FP32 if stage else 0)
+        print("k_search", dtype, kind, "staged" if stage else "in place", flush=True)
+        with tno.Search(0, tune_cache_path=str(path)) as h:
+            g, res = tno.search_tensors(codes, _to(sigma), _to(times), _to(vel), t_ref=float(times[0]),
+                                        handle=h, flags=flags, **kw)
+        torch.cuda.synchronize()
+        assert res.status == 0, res.message
+        got[stage] = (g["snr"].cpu().numpy(), g["flux"].cpu().numpy(), tno.decode_candidates(g["topk"], res.n_topk))
+    assert np.array_equal(got[False][0], got[True][0]) and np.array_equal(got[False][1], got[True][1])
+    assert got[False][2] == got[True][2]
+    npdt = np.uint8 if dtype == "fp8_e4m3" else np.uint16
+    deq = codec.dequantize(codes.cpu().numpy().view(npdt), sc.cpu().numpy(), dtype)
+    o = oracle.search(deq, sigma, times, float(times[0]), vel, **okw)
+    parity.check_maps(got[False][0], got[False][1], o)
+
+
 @pytest.mark.parametrize("variant", ["ws", "ws4"])
 @pytest.mark.parametrize("stamp,kind", [(1, 0), (3, 0), (5, 0), (5, 1), (3, "table"), (5, "table")])
 def test_wave_shift_variant_stamps_and_edges(tmp_path, stamp, kind, variant):
