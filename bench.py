@@ -490,7 +490,8 @@ def batched_form(dev, autotune=True):
         name = "staged_fp32" if stage else "in_place"
         log("batched form (%s): %.1f ms per request (search %.1f ms), tuning request %.1f ms, tuned %s"
             % (name, dm, sm, first.device_ms, tuned))
-        res[name] = {"device_ms": dm, "search_ms": sm, "updates_per_s": U / (dm * 1e-3),
+        lm = float(np.mean([x.lambda_ms for x in runs]))
+        res[name] = {"device_ms": dm, "search_ms": sm, "lambda_ms": lm, "updates_per_s": U / (dm * 1e-3),
                      "search_TFLOPs": 20 * U / (sm * 1e-3) / 1e12,
                      "first_request_ms_with_autotune" if autotune else "first_request_ms": first.device_ms,
                      "tuned": tuned[0].split()[2:4] if tuned else None,

@@ -505,6 +505,13 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
                     if (p.trail[p.rows[a]].tr == o2)
                         p.jlist.push_back(p.rows[a]);
                 sl.nj[o2] = (int)p.jlist.size() - sl.joff[o2];
+                // the normaliser's work items run tile by tile with these
+                // trajectories fastest: the costliest trail kernels (major
+                // lines x run capacity) first, so that the items dispatched
+                // last are the short ones and the launch ends with a short tail
+                auto cost = [&](int32_t j) { return (int64_t)p.trail[j].ncols * (p.trail[j].cap + 31); };
+                std::stable_sort(p.jlist.begin() + sl.joff[o2], p.jlist.end(),
+                                 [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
             }
         }
     }
