@@ -74,7 +74,13 @@ struct TopkState {
     int32_t k_rem;     // rank still to find among keys matching prefix
     uint32_t n_gt;     // candidates strictly above the threshold written
     uint32_t hist[256];
+    // the pruned selection of a slab: the k-th largest tile maximum, the
+    // entries gathered from the tiles that reach it, and whether it produced
+    // the slab's top k (the full selection's passes then return at once)
+    uint32_t tstar, n_cand, skip, pad;
 };
+// Entries the pruned selection sorts in one block.
+constexpr int TOPK_GATHER_CAP = 4096;
 
 struct SearchArgs {
     const float4 *Z4;        // padded inverse-variance-weighted stack [T][Hp][Wp4] float4
@@ -186,9 +192,13 @@ hipError_t launch_best(hipStream_t st, int J, int64_t HW, const int32_t *rows, b
                        const float *flux, float *best_snr, int32_t *best_traj, float *best_flux);
 // The exact top k of one slab's N = J*HW scores merged into the k_run
 // candidates kept in topk_out from earlier slabs (0: none).
+// (Pruned by the slab's tile maxima: tiles of tx x ty start pixels, ntx per
+// row, their keys in tile_keys [trajectory][ntiles]; gbuf holds
+// TOPK_GATHER_CAP (key, index) pairs.)
 hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int64_t N, int64_t HW,
-                       int W, const int32_t *rows, int k, int k_run, TopkState *state, uint32_t *chunk_cnt,
-                       int64_t n_chunks, uint64_t *cand, void *topk_out);
+                       int H, int W, const int32_t *rows, int k, int k_run, const uint64_t *tile_keys,
+                       int ntiles, int ntx, int tx, int ty, uint64_t *gbuf, TopkState *state,
+                       uint32_t *chunk_cnt, int64_t n_chunks, uint64_t *cand, void *topk_out);
 // Row r of a slab's map (J rows of HW values) into row rows[r] of a map with
 // a row per trajectory.
 hipError_t launch_rows_out(hipStream_t st, int J, int64_t HW, const int32_t *rows, const float *slab_map,

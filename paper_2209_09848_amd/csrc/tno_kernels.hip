@@ -1293,8 +1293,11 @@ hipError_t launch_rows_out(hipStream_t st, int J, int64_t HW, const int32_t *row
 // 3) chunk counts + a scan give each K*-valued element its rank in index
 //    order, and the first `need` are appended; 4) one block sorts the k.
 
-__global__ void k_topk_init(TopkState *st, int k, uint64_t *cand)
+// honor: return at once when the pruned selection already produced the top k.
+__global__ void k_topk_init(TopkState *st, int k, uint64_t *cand, int honor)
 {
+    if (honor && st->skip)
+        return;
     if (threadIdx.x == 0) {
         st->prefix = 0;
         st->mask = 0;
@@ -1307,8 +1310,10 @@ __global__ void k_topk_init(TopkState *st, int k, uint64_t *cand)
         cand[i] = 0;
 }
 
-__global__ void k_topk_hist(const float *__restrict__ snr, int64_t N, TopkState *st, int shift)
+__global__ void k_topk_hist(const float *__restrict__ snr, int64_t N, TopkState *st, int shift, int honor)
 {
+    if (honor && st->skip)
+        return;
     __shared__ uint32_t hl[256];
     for (int i = threadIdx.x; i < 256; i += blockDim.x)
         hl[i] = 0;
@@ -1326,8 +1331,10 @@ __global__ void k_topk_hist(const float *__restrict__ snr, int64_t N, TopkState 
             atomicAdd(&st->hist[i], hl[i]);
 }
 
-__global__ void k_topk_select(TopkState *st, int shift)
+__global__ void k_topk_select(TopkState *st, int shift, int honor)
 {
+    if (honor && st->skip)
+        return;
     if (threadIdx.x == 0) {
         int32_t krem = st->k_rem;
         uint32_t above = 0;
@@ -1349,8 +1356,10 @@ __global__ void k_topk_select(TopkState *st, int shift)
 
 // Append keys > K*; count K*-valued keys per chunk of TOPK_CHUNK elements.
 __global__ void k_topk_gt(const float *__restrict__ snr, int64_t N, int k, TopkState *st,
-                          uint32_t *__restrict__ chunk_cnt, uint64_t *__restrict__ cand)
+                          uint32_t *__restrict__ chunk_cnt, uint64_t *__restrict__ cand, int honor)
 {
+    if (honor && st->skip)
+        return;
     const uint32_t kstar = st->prefix;
     const int64_t c0 = (int64_t)blockIdx.x * TOPK_CHUNK;
     uint32_t ties = 0;
@@ -1377,8 +1386,10 @@ __global__ void k_topk_gt(const float *__restrict__ snr, int64_t N, int k, TopkS
 }
 
 // Exclusive scan of the chunk counts (one block).
-__global__ void k_topk_scan(uint32_t *cnt, int64_t n)
+__global__ void k_topk_scan(uint32_t *cnt, int64_t n, const TopkState *st, int honor)
 {
+    if (honor && st->skip)
+        return;
     __shared__ uint32_t carry;
     __shared__ uint32_t buf[256];
     if (threadIdx.x == 0)
@@ -1408,8 +1419,10 @@ __global__ void k_topk_scan(uint32_t *cnt, int64_t n)
 // Append the first `need` K*-valued elements in index order.
 __global__ void k_topk_ties(const float *__restrict__ snr, int64_t N, int k,
                             const TopkState *__restrict__ st,
-                            const uint32_t *__restrict__ chunk_off, uint64_t *__restrict__ cand)
+                            const uint32_t *__restrict__ chunk_off, uint64_t *__restrict__ cand, int honor)
 {
+    if (honor && st->skip)
+        return;
     const uint32_t kstar = st->prefix;
     const uint32_t need = (uint32_t)st->k_rem;
     const uint32_t n_gt = (uint32_t)k - need;
@@ -1538,28 +1551,165 @@ __global__ __launch_bounds__(1024) void k_topk_merge(int k_new, int k_run, int k
 
 // Radix select + tie resolution of the k largest keys of `vals` (N values);
 // leaves the k (key, index) pairs, unsorted, in cand.
+// honor: every pass returns at once if the pruned selection set state->skip.
 static void topk_select(hipStream_t st, const float *vals, int64_t N, int k, TopkState *state,
-                        uint32_t *chunk_cnt, int64_t n_chunks, uint64_t *cand)
+                        uint32_t *chunk_cnt, int64_t n_chunks, uint64_t *cand, int honor)
 {
-    hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(256), 0, st, state, k, cand);
+    hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(256), 0, st, state, k, cand, honor);
     int64_t blocks = (N + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     for (int pass = 0; pass < 4; ++pass) {
         int shift = 24 - 8 * pass;
-        hipLaunchKernelGGL(k_topk_hist, dim3((unsigned)blocks), dim3(256), 0, st, vals, N, state, shift);
-        hipLaunchKernelGGL(k_topk_select, dim3(1), dim3(256), 0, st, state, shift);
+        hipLaunchKernelGGL(k_topk_hist, dim3((unsigned)blocks), dim3(256), 0, st, vals, N, state, shift, honor);
+        hipLaunchKernelGGL(k_topk_select, dim3(1), dim3(256), 0, st, state, shift, honor);
     }
-    hipLaunchKernelGGL(k_topk_gt, dim3((unsigned)n_chunks), dim3(256), 0, st, vals, N, k, state, chunk_cnt, cand);
-    hipLaunchKernelGGL(k_topk_scan, dim3(1), dim3(256), 0, st, chunk_cnt, n_chunks);
-    hipLaunchKernelGGL(k_topk_ties, dim3((unsigned)n_chunks), dim3(256), 0, st, vals, N, k, state, chunk_cnt, cand);
+    hipLaunchKernelGGL(k_topk_gt, dim3((unsigned)n_chunks), dim3(256), 0, st, vals, N, k, state, chunk_cnt, cand,
+                       honor);
+    hipLaunchKernelGGL(k_topk_scan, dim3(1), dim3(256), 0, st, chunk_cnt, n_chunks, state, honor);
+    hipLaunchKernelGGL(k_topk_ties, dim3((unsigned)n_chunks), dim3(256), 0, st, vals, N, k, state, chunk_cnt, cand,
+                       honor);
+}
+
+// Pruned selection of one slab's top k.  The tile keys hold each (tile,
+// trajectory) maximum, and k of them are elements of the slab, so the k-th
+// largest tile maximum T* is at most the slab's k-th largest score: every
+// entry of the top k has a key of at least T* and lies in a tile whose
+// maximum reaches T*.  Those entries are gathered and, if there are few
+// enough, sorted in one block; otherwise the full selection runs.
+
+// One block: T* by four 8-bit radix passes over the slab's tile keys (rows
+// of the slab, all tiles); resets the gather count and the skip flag.
+__global__ __launch_bounds__(1024) void k_tile_threshold(const int32_t *__restrict__ rows, int nj, int ntiles,
+                                                         const uint64_t *__restrict__ tile_keys, int k,
+                                                         TopkState *st)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t s_prefix, s_mask;
+    __shared__ int32_t s_krem;
+    const int64_t n = (int64_t)nj * ntiles;
+    if (threadIdx.x == 0) {
+        s_prefix = 0;
+        s_mask = 0;
+        s_krem = k;
+    }
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        for (int i = threadIdx.x; i < 256; i += blockDim.x)
+            hist[i] = 0;
+        __syncthreads();
+        const uint32_t prefix = s_prefix, mask = s_mask;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const int64_t r = i / ntiles;
+            const uint32_t key = (uint32_t)(tile_keys[(int64_t)rows[r] * ntiles + (i - r * ntiles)] >> 32);
+            if ((key & mask) == prefix)
+                atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t above = 0;
+            int b = 255;
+            for (; b > 0; --b) {
+                const uint32_t c = hist[b];
+                if ((int64_t)above + c >= (int64_t)s_krem)
+                    break;
+                above += c;
+            }
+            s_prefix |= (uint32_t)b << shift;
+            s_mask |= 255u << shift;
+            s_krem -= (int32_t)above;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->tstar = n >= k ? s_prefix : 0u;   // fewer tiles than k: every entry qualifies
+        st->n_cand = 0;
+        st->skip = 0;
+    }
+}
+
+// One block per (slab row, tile): a tile whose maximum reaches T* appends
+// every entry with a key of at least T* as (key, index in the slab's map).
+__global__ void k_tile_gather(const int32_t *__restrict__ rows, int ntiles, int ntx, int tx, int ty, int H, int W,
+                              int64_t HW, const uint64_t *__restrict__ tile_keys, const float *__restrict__ snr,
+                              TopkState *st, uint64_t *__restrict__ buf)
+{
+    const int r = blockIdx.x / ntiles, t = blockIdx.x - r * ntiles;
+    const uint32_t tstar = st->tstar;
+    if ((uint32_t)(tile_keys[(int64_t)rows[r] * ntiles + t] >> 32) < tstar)
+        return;
+    const int tyi = t / ntx, txi = t - tyi * ntx;
+    const int y0 = tyi * ty, x0 = txi * tx;
+    const int th = min(ty, H - y0), tw = min(tx, W - x0);
+    for (int i = threadIdx.x; i < th * tw; i += blockDim.x) {
+        const int yy = i / tw;
+        const int64_t li = (int64_t)r * HW + (int64_t)(y0 + yy) * W + (x0 + i - yy * tw);
+        const uint32_t key = ordered_key(snr[li]);
+        if (key >= tstar) {
+            const uint32_t pos = atomicAdd(&st->n_cand, 1u);
+            if (pos < (uint32_t)TOPK_GATHER_CAP) {
+                buf[2 * pos] = key;
+                buf[2 * pos + 1] = (uint64_t)li;
+            }
+        }
+    }
+}
+
+// One block: if at most TOPK_GATHER_CAP entries were gathered, sort them
+// (key descending, index ascending), write the first k to cand and set
+// skip; otherwise leave skip 0 for the full selection.
+__global__ __launch_bounds__(1024) void k_topk_small(const uint64_t *__restrict__ buf, int k, TopkState *st,
+                                                     uint64_t *__restrict__ cand)
+{
+    __shared__ uint32_t sk[TOPK_GATHER_CAP];
+    __shared__ uint64_t si[TOPK_GATHER_CAP];
+    const uint32_t n = st->n_cand;
+    if (n > (uint32_t)TOPK_GATHER_CAP || n < (uint32_t)k)
+        return;
+    int np = 1;
+    while (np < (int)n)
+        np <<= 1;
+    for (int t = threadIdx.x; t < np; t += blockDim.x) {
+        const bool in = t < (int)n;
+        sk[t] = in ? (uint32_t)buf[2 * t] : 0u;     // padding: the smallest key, the largest index
+        si[t] = in ? buf[2 * t + 1] : ~0ull;
+    }
+    __syncthreads();
+    for (int size = 2; size <= np; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < np; t += blockDim.x) {
+                const int p = t ^ stride;
+                if (p > t) {
+                    const bool t_before_p = sk[t] > sk[p] || (sk[t] == sk[p] && si[t] < si[p]);
+                    const bool ascending = (t & size) == 0;
+                    if (ascending != t_before_p) {
+                        const uint32_t a = sk[t]; sk[t] = sk[p]; sk[p] = a;
+                        const uint64_t b = si[t]; si[t] = si[p]; si[p] = b;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        cand[2 * t] = sk[t];
+        cand[2 * t + 1] = si[t];
+    }
+    if (threadIdx.x == 0)
+        st->skip = 1;
 }
 
 hipError_t launch_topk(hipStream_t st, const float *snr, const float *flux, int64_t N, int64_t HW,
-                       int W, const int32_t *rows, int k, int k_run, TopkState *state, uint32_t *chunk_cnt,
-                       int64_t n_chunks, uint64_t *cand, void *topk_out)
+                       int H, int W, const int32_t *rows, int k, int k_run, const uint64_t *tile_keys,
+                       int ntiles, int ntx, int tx, int ty, uint64_t *gbuf, TopkState *state,
+                       uint32_t *chunk_cnt, int64_t n_chunks, uint64_t *cand, void *topk_out)
 {
     const int k_new = (int)std::min<int64_t>(k, N);
-    topk_select(st, snr, N, k_new, state, chunk_cnt, n_chunks, cand);
+    const int nj = (int)(N / HW);
+    hipLaunchKernelGGL(k_tile_threshold, dim3(1), dim3(1024), 0, st, rows, nj, ntiles, tile_keys, k_new, state);
+    hipLaunchKernelGGL(k_tile_gather, dim3((unsigned)(nj * ntiles)), dim3(256), 0, st, rows, ntiles, ntx, tx, ty, H,
+                       W, HW, tile_keys, snr, state, gbuf);
+    hipLaunchKernelGGL(k_topk_small, dim3(1), dim3(1024), 0, st, gbuf, k_new, state, cand);
+    topk_select(st, snr, N, k_new, state, chunk_cnt, n_chunks, cand, 1);
     hipLaunchKernelGGL(k_topk_merge, dim3(1), dim3(1024), 0, st, k_new, k_run, std::min(k, k_run + k_new), N,
                        HW, W, rows, cand, flux, (tno_candidate *)topk_out);
     return hipGetLastError();
@@ -1767,7 +1917,7 @@ hipError_t launch_significance(hipStream_t st, int H, int W, int box, float thr,
     int blocks = (int)std::min<int64_t>((HW + 255) / 256, 4096);
     hipLaunchKernelGGL(k_count_above, dim3(blocks), dim3(256), 0, st, HW, sig, thr, counts);
     if (k > 0) {
-        topk_select(st, sig, HW, k, state, chunk_cnt, n_chunks, cand);
+        topk_select(st, sig, HW, k, state, chunk_cnt, n_chunks, cand, 0);
         hipLaunchKernelGGL(k_detect_final, dim3(1), dim3(TNO_MAX_TOPK), 0, st, HW, W, k, thr, cand,
                            best_snr, best_traj, best_flux, det, counts + 1);
     }

@@ -128,7 +128,7 @@ struct Plan {
            o_iv64 = 0, o_tab32 = 0, o_tab64 = 0, o_trail = 0, o_colmeta = 0, o_kvals = 0,
            o_err = 0, o_lam = 0, o_snr = 0, o_flux = 0, o_tkeys = 0, o_tstate = 0, o_chunks = 0,
            o_cand = 0, o_tmax = 0, o_topk = 0, o_best = 0, o_bestj = 0, o_bestf = 0, o_perm = 0, o_rows = 0,
-           o_jrow = 0, o_snr_full = 0, o_flux_full = 0, o_r1 = 0,
+           o_jrow = 0, o_snr_full = 0, o_flux_full = 0, o_gbuf = 0, o_r1 = 0,
            o_r2 = 0, o_b1 = 0, o_b2 = 0, o_sig = 0, o_det = 0, o_counts = 0, o_prf = 0, o_jit = 0,
            o_jl = 0, bytes = 0;
 };
@@ -572,6 +572,7 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     p.o_tstate = take(sizeof(tno::TopkState));
     p.o_chunks = take((size_t)p.n_chunks * 4);
     p.o_cand = take((size_t)TNO_MAX_TOPK * 16);
+    p.o_gbuf = take((size_t)tno::TOPK_GATHER_CAP * 16);
     p.o_tmax = take(J * sizeof(tno_peak));
     p.o_topk = take((size_t)TNO_MAX_TOPK * sizeof(tno_candidate));
     p.o_best = take(HW * 4);
@@ -1064,7 +1065,9 @@ hipError_t enqueue_slab_reduce(Request *q, int s)
                          at<int32_t>(A, p.o_bestj), at<float>(A, p.o_bestf)));
     if (p.k > 0) {
         const int k_run = (int)std::min<int64_t>(p.k, (int64_t)sl.a0 * HW);   // kept from earlier slabs
-        TRY(tno::launch_topk(st, snr, flux, (int64_t)nj * HW, HW, p.W, rows, p.k, k_run,
+        TRY(tno::launch_topk(st, snr, flux, (int64_t)nj * HW, HW, p.H, p.W, rows, p.k, k_run,
+                             at<uint64_t>(A, p.o_tkeys), p.ntiles, p.ntx, tno::search_tx(p.variant),
+                             tno::search_ty(p.variant), at<uint64_t>(A, p.o_gbuf),
                              at<tno::TopkState>(A, p.o_tstate), at<uint32_t>(A, p.o_chunks), p.n_chunks,
                              at<uint64_t>(A, p.o_cand), at<void>(A, p.o_topk)));
     }

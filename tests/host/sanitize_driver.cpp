@@ -34,8 +34,9 @@ hipError_t launch_trajmax(hipStream_t, int, int, int, int, const int32_t *, cons
                           const float *, void *) { return hipErrorNotSupported; }
 hipError_t launch_best(hipStream_t, int, int64_t, const int32_t *, bool, const float *, const float *, float *,
                        int32_t *, float *) { return hipErrorNotSupported; }
-hipError_t launch_topk(hipStream_t, const float *, const float *, int64_t, int64_t, int, const int32_t *, int,
-                       int, TopkState *, uint32_t *, int64_t, uint64_t *, void *) { return hipErrorNotSupported; }
+hipError_t launch_topk(hipStream_t, const float *, const float *, int64_t, int64_t, int, int, const int32_t *, int,
+                       int, const uint64_t *, int, int, int, int, uint64_t *, TopkState *, uint32_t *, int64_t,
+                       uint64_t *, void *) { return hipErrorNotSupported; }
 hipError_t launch_rows_out(hipStream_t, int, int64_t, const int32_t *, const float *, float *)
 {
     return hipErrorNotSupported;
