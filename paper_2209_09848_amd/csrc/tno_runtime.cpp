@@ -234,7 +234,7 @@ int default_variant(const Plan &p)
 {
     if (!p.direct)
         return 0;
-    return p.dtype == TNO_FP8_E4M3 && p.S == 5 ? 0 : tno::SEARCH_WS;
+    return p.S == 5 ? 0 : tno::SEARCH_WS;
 }
 
 void set_search_shape(Plan &p, int v, int tblock)
@@ -362,13 +362,15 @@ Fail make_plan(const tno_request *r, const tno_outputs *o, const double *times,
     // the wave-shift search serves the stamp, unless the caller asks for the
     // staged copy
     p.direct = p.dtype != TNO_F32 && (r->flags & TNO_REQ_STAGE_FP32) == 0 && direct_ok(p);
-    // untuned default: the first tile shape (for a stack read in place the
-    // wave-shift shape, except FP8 codes with stamp 5, which the first shape
-    // reads faster: on the FFI workload 238 against 272 ms, where BF16 takes
-    // 261 against 255), trajectories in blocks of 16 (on the 100-trajectory
-    // FFI bank 2.7 % faster than one block of all, and blocks of 8 are 25 %
-    // slower: fewer trajectories of a tile run together and share its windows
-    // in L2)
+    // untuned default: the first tile shape, also for a stack read in place
+    // with stamp 5 (other stamps: the wave-shift shape).  Its tiles are 128
+    // columns wide against the wave-shift kernel's 124, which wastes 45 % of
+    // a 256-px cutout (3 tiles), and it reads FP8 faster: on the serving mix
+    // BF16 p99 242-261 against 283-298 ms, on the FFI workload FP8 238
+    // against 272 ms (BF16 261 against 255).  Trajectories in blocks of 16
+    // (on the 100-trajectory FFI bank 2.7 % faster than one block of all, and
+    // blocks of 8 are 25 % slower: fewer trajectories of a tile run together
+    // and share its windows in L2)
     set_search_shape(p, default_variant(p), DEFAULT_TBLOCK);
     p.ntiles_max = ((W + 63) / 64) * ((H + 15) / 16);
     // search order: trajectories adjacent in the work order should have nearby

@@ -43,9 +43,9 @@ def test_stream_results_equal_alone(mode, slab_bytes):
     print("stats", stats, flush=True)
     assert len(recs) == 20
     if mode == "batch":
-        # every work item (124 x 32 tile, trajectory: the in-place BF16 search's
+        # every work item (128 x 32 tile, trajectory: the in-place BF16 search's
         # shape) went through a step, and steps served several requests at once
-        items = sum(-(-r["side"] // 124) * -(-r["side"] // 32) * r["traj"] for r in recs)
+        items = sum(-(-r["side"] // 128) * -(-r["side"] // 32) * r["traj"] for r in recs)
         assert stats["batch_items"] == items
         assert stats["batch_steps"] > 0 and stats["batch_shared"] > 0
     pool = serve.StackPool(shapes, "bf16", DEV)
