@@ -615,17 +615,25 @@ def test_wave_shift_variant_stamps_and_edges(tmp_path, stamp, kind, variant):
 
 
 def test_autotune_writes_cache_and_keeps_results(tmp_path):
+    """Autotuning (which times candidates on the request's own buffers) leaves
+    the request's results as a plain run of the chosen variant gives them,
+    and those match the oracle."""
     R, sigma, times, vel = _rand_problem(81, 60, 100, 260, 20)
-    ref, _ = run_gpu(R, sigma, times, vel, float(times[0]), top_k=10)
     path = tmp_path / "tune.txt"
     with tno.Search(0, autotune=True, tune_cache_path=str(path)) as h:
         g, res = run_gpu(R, sigma, times, vel, float(times[0]), top_k=10, handle=h)
-    assert np.array_equal(g["snr"], ref["snr"])
     lines = [l for l in path.read_text().splitlines() if not l.startswith("#")]
     assert len(lines) == 1
     arch, cls, name, tb, rate = lines[0].split()
     assert arch == _arch() and cls == tno.shape_class(100, 260, 60, 20)
     assert name in tno.SEARCH_VARIANTS and 1 <= int(tb) <= 20 and float(rate) > 0
+    print("tuned", name, tb, flush=True)
+    with tno.Search(0, tune_cache_path=_forced(tmp_path, name, int(tb), 100, 260, 60, 20)) as h:
+        ref, _ = run_gpu(R, sigma, times, vel, float(times[0]), top_k=10, handle=h)
+    assert np.array_equal(g["snr"], ref["snr"]) and np.array_equal(g["flux"], ref["flux"])
+    assert g["topk"] == ref["topk"]
+    o = oracle.search(R, sigma, times, float(times[0]), vel)
+    parity.check_maps(g["snr"], g["flux"], o)
 
 
 # ------------------------------------------------------------------ Sec. 3.3 significance (next row)
