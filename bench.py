@@ -114,6 +114,12 @@ def main():
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched form, untuned (default tile shape), and print its result")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving form and print its result")
+    ap.add_argument("--serving-side", type=int, default=1024,
+                    help="largest cutout side of the serving form (multiples of 256 from 256)")
+    ap.add_argument("--serving-requests", type=int, default=300,
+                    help="measured requests per serving form (after a tenth as many warm-up ones)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the untimed side measurements (tabulated PRF, background re-fit)")
     args = ap.parse_args()
@@ -134,6 +140,10 @@ def main():
 
     if args.batched_only:
         print(json.dumps(batched_form(dev, autotune=False)))
+        return
+    if args.serving_only:
+        print(json.dumps(serving_form(n_requests=args.serving_requests, warm=max(1, args.serving_requests // 10),
+                                      max_side=args.serving_side)))
         return
 
     if args.copy_probe:
@@ -408,27 +418,33 @@ def precision_forms(R, sig_t, times_t, vel_t, t_ref, k, out, dev, U):
     return res
 
 
-def serving_form(n_requests=48, warm=8, load=0.7, max_side=1024, seed=0):
+def serving_form(n_requests=300, warm=30, load=0.7, max_side=1024, n_keys=32, seed=0):
     """A Poisson stream of uneven requests (cutouts 256..max_side px, 200-1000
-    frames, 16-256 trajectories of the shell bank; stacks resident under keys,
-    about half the requests reusing one) at `load` times the back-to-back
-    capacity of the plain FP32 search on a sample of the mix; FP32, BF16 read
-    in place and BF16 staged into FP32 per request, each with eager
-    per-request launches and with continuous batching, at the same arrival
-    rate."""
+    frames, 16-256 trajectories of the shell bank; stacks resident under
+    `n_keys` keys, about half the requests reusing the previous one) at `load`
+    times the back-to-back capacity of the plain FP32 search on a sample of
+    the mix; FP32, BF16 read in place and BF16 staged into FP32 per request,
+    each with eager per-request launches and with continuous batching, at the
+    same arrival rate."""
     import numpy as np
 
     from paper_2209_09848_amd import serve, synth
     bank, _ = synth.grid_shells()
     sides = list(range(256, max_side + 1, 256))
-    shapes = serve.draw_stack_shapes(8, seed, sides=sides)
+    shapes = serve.draw_stack_shapes(n_keys, seed, sides=sides)
     specs = serve.draw_requests(n_requests + warm, shapes, bank.shape[0], seed)
-    cal = [serve.Spec(s.key, s.side, s.frames, s.traj_idx, 0.0) for s in specs[:8]]
+    # capacity: updates/s of the plain FP32 search back to back on a sample of
+    # the mix; the arrival rate offers `load` times that in the mix's mean
+    # updates per request
+    cal = [serve.Spec(s.key, s.side, s.frames, s.traj_idx, 0.0) for s in specs[:16]]
     crec = serve.run_stream(cal, bank, dtype="f32", max_inflight=1)
-    mean_s = float(np.mean([x["device_ms"] for x in crec])) * 1e-3
-    rate = load / mean_s
-    out = {"workload": "%d requests (+%d warm-up), cutouts 256-%d px, 200-1000 frames, 16-256 trajectories"
-                       % (n_requests, warm, max_side), "load": load, "arrival_rate_per_s": rate, "forms": {}}
+    cap = sum(x["updates"] for x in crec) / (sum(x["device_ms"] for x in crec) * 1e-3)
+    mean_u = float(np.mean([len(s.traj_idx) * s.side * s.side * s.frames for s in specs]))
+    rate = load * cap / mean_u
+    out = {"workload": "%d requests (+%d warm-up), cutouts 256-%d px, 200-1000 frames, 16-256 trajectories, "
+                       "%d stack keys" % (n_requests, warm, max_side, n_keys),
+           "load": load, "arrival_rate_per_s": rate, "capacity_updates_per_s": cap,
+           "mean_updates_per_request": mean_u, "forms": {}}
     for dtype, stage in (("f32", False), ("bf16", False), ("bf16", True)):
         for mode in ("eager", "batch"):
             sp = serve.poisson_arrivals([serve.Spec(s.key, s.side, s.frames, s.traj_idx) for s in specs],

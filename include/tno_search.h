@@ -41,8 +41,10 @@ extern "C" {
 #define TNO_OK 0
 #define TNO_PENDING 1          /* poll only: work not finished yet */
 #define TNO_E_INVAL (-1)       /* bad argument (message says which) */
-#define TNO_E_NOMEM (-2)       /* footprint can never fit the HBM budget, or allocation failed */
-#define TNO_E_BUSY (-3)        /* in-flight limit or budget full right now; retry later */
+#define TNO_E_NOMEM (-2)       /* footprint can never fit the HBM budget, or allocation failed
+                                  with nothing in flight */
+#define TNO_E_BUSY (-3)        /* in-flight limit or budget full right now, or allocation failed
+                                  while requests are in flight; retry later */
 #define TNO_E_DEVICE (-4)      /* HIP runtime or kernel error */
 #define TNO_E_TICKET (-5)      /* unknown ticket, or already collected */
 #define TNO_E_CANCELLED (-6)   /* request cancelled */
@@ -250,7 +252,10 @@ int tno_search_create(const tno_config *cfg, tno_search **out_handle);
  * returns; with TNO_REQ_DEVICE_PTRS inputs are borrowed until the terminal
  * poll and must stay unmodified.  Returns TNO_OK and writes *out_ticket, or
  * TNO_E_INVAL / TNO_E_NOMEM / TNO_E_BUSY / TNO_E_DEVICE; on error nothing is
- * enqueued.  tno_search_last_error() holds the message of a refusal. */
+ * enqueued.  tno_search_last_error() holds the message of a refusal.  A device
+ * allocation that fails (memory held outside the handle) first frees the
+ * handle's cached blocks, then its idle resident stacks, least recently used
+ * first. */
 int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *out,
                       uint64_t *out_ticket);
 

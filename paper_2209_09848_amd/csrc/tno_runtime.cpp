@@ -801,7 +801,29 @@ bool make_room(tno_search *h, size_t need)
     return true;
 }
 
-// A device block of at least `bytes` from the cache, else hipMalloc.
+// Drop the least recently used idle resident stack (its block is freed).
+// Returns false if every resident stack is in use.
+bool evict_one(tno_search *h)
+{
+    Stack *victim = nullptr;
+    for (auto &kv : h->stacks)
+        if (kv.second->refs == 0 && (!victim || kv.second->last_use < victim->last_use))
+            victim = kv.second;
+    if (!victim)
+        return false;
+    h->stacks.erase(victim->key);
+    (void)hipFree(victim->block);
+    h->in_use -= victim->bytes;
+    if (victim->ready)
+        (void)hipEventDestroy(victim->ready);
+    delete victim;
+    return true;
+}
+
+// A device block of at least `bytes` from the cache, else hipMalloc.  The
+// device can be short of memory inside the budget (other users of the GPU):
+// then the cached blocks are freed, then idle resident stacks one at a time,
+// before the allocation is given up.
 void *get_block(tno_search *h, size_t bytes, size_t *got)
 {
     void *p = h->cache.take(bytes, got);
@@ -812,9 +834,10 @@ void *get_block(tno_search *h, size_t bytes, size_t *got)
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         h->cache.trim(0);
-        if (hipMalloc(&p, bytes) != hipSuccess) {
+        while (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
-            return nullptr;
+            if (!evict_one(h))
+                return nullptr;
         }
     }
     *got = bytes;
@@ -1694,8 +1717,11 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
         if (st)
             st->refs -= 1;
         delete q;
-        set_last(fail(TNO_E_NOMEM, "device allocation of %.3g GB failed", p.bytes / 1e9));
-        return TNO_E_NOMEM;
+        // with requests in flight their memory comes back: retry later
+        const int code = h->live.empty() ? TNO_E_NOMEM : TNO_E_BUSY;
+        set_last(fail(code, "device allocation of %.3g GB failed%s", p.bytes / 1e9,
+                      code == TNO_E_BUSY ? " while requests are in flight" : ""));
+        return code;
     }
     h->in_use += q->arena_bytes;
     q->sev.assign(3 * p.slabs.size(), nullptr);
@@ -1716,8 +1742,10 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
         if (!blk) {
             delete ns;
             release(h, q);
-            set_last(fail(TNO_E_NOMEM, "device allocation of a %.3g GB stack failed", p.stack_bytes / 1e9));
-            return TNO_E_NOMEM;
+            const int code = h->live.empty() ? TNO_E_NOMEM : TNO_E_BUSY;
+            set_last(fail(code, "device allocation of a %.3g GB stack failed%s", p.stack_bytes / 1e9,
+                          code == TNO_E_BUSY ? " while requests are in flight" : ""));
+            return code;
         }
         ns->key = req->stack_key;
         ns->H = p.H;

@@ -141,6 +141,7 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
                    hbm_budget_bytes=int(budget_gb * 1e9), graphs=mode == "graphs", batch=mode == "batch",
                    slab_bytes=slab_bytes)
     t0 = time.perf_counter()
+    retried = False
     try:
         while pending or queue or inflight:
             now = time.perf_counter() - t0
@@ -169,8 +170,15 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
                 if rc == tno.TNO_E_INVAL and R is None:
                     known.discard(s.key)   # evicted by the library: hand the stack over again
                     continue
+                if rc == tno.TNO_E_NOMEM and not retried:
+                    # nothing in flight: device memory is held by torch's cache
+                    # (stacks already handed over); return it and try once more
+                    retried = True
+                    torch.cuda.empty_cache()
+                    continue
                 if rc != tno.TNO_OK:
                     raise tno.TnoError(rc, tno.tno_search_last_error())
+                retried = False
                 known.add(s.key)
                 staged.pop(s.key, None)
                 inflight[ticket] = (s, o, vel, R, scales)
