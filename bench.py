@@ -426,9 +426,20 @@ def serving_form(n_requests=300, warm=30, load=0.7, max_side=1024, n_keys=32, se
     the mix; FP32, BF16 read in place and BF16 staged into FP32 per request,
     each with eager per-request launches and with continuous batching, at the
     same arrival rate."""
+    import gc
+
     import numpy as np
+    import torch
 
     from paper_2209_09848_amd import serve, synth
+    if max_side > serve.MAX_SIDE:
+        # with cutouts to 2048 px the serving driver's own stack copies and the
+        # library's budget together exhausted device memory: the HIP runtime
+        # aborted its queues (out of resources) and the run hung
+        raise ValueError("serving cutouts above %d px are disabled: device memory of the driver's "
+                         "stack copies and the library's budget is not yet bounded together" % serve.MAX_SIDE)
+    gc.collect()
+    torch.cuda.empty_cache()   # each form's handle takes its budget from the free memory
     bank, _ = synth.grid_shells()
     sides = list(range(256, max_side + 1, 256))
     shapes = serve.draw_stack_shapes(n_keys, seed, sides=sides)

@@ -112,7 +112,10 @@ typedef struct tno_search tno_search;   /* opaque handle */
 typedef struct {
     int32_t device;              /* HIP device ordinal */
     int32_t max_inflight;        /* tickets admitted at once (<= 0: 64) */
-    uint64_t hbm_budget_bytes;   /* device bytes the handle may hold (0: 90% of free) */
+    uint64_t hbm_budget_bytes;   /* device bytes the handle may hold (0: 90% of the memory
+                                    free at create; a caller that allocates device memory
+                                    after creating the handle passes a budget that leaves
+                                    room for it and for the HIP runtime's own needs) */
     uint32_t flags;              /* TNO_CFG_* */
     uint32_t reserved;           /* must be 0 */
     void *stream;                /* hipStream_t to run on, or NULL for an own stream */

@@ -101,19 +101,26 @@ class StackPool:
         sig, _ = self.inputs(key)
         gen = torch.Generator(device=self.device)
         gen.manual_seed(key)
-        R = torch.randn((frames, side, side), generator=gen, device=self.device) * sig
+        R = torch.randn((frames, side, side), generator=gen, device=self.device)
+        R.mul_(sig)   # in place: the draw holds one stack-sized buffer
         if self.dtype == "f32":
             return R, None
         codes = torch.empty((frames, side, side), device=self.device,
                             dtype=torch.uint8 if self.dtype == "fp8_e4m3" else torch.int16)
         scales = torch.empty((frames, (side + 63) // 64, (side + 63) // 64), device=self.device)
         rc = tno.tno_quantize(frames, side, side, tno.DTYPE_CODE[self.dtype], R.data_ptr(),
-                              codes.data_ptr(), scales.data_ptr(), None)
+                              codes.data_ptr(), scales.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream)
         if rc != 0:
             raise tno.TnoError(rc, tno.tno_search_last_error())
-        torch.cuda.synchronize()
+        torch.cuda.current_stream().synchronize()
         del R
         return codes, scales
+
+
+HANDOVERS = 2                  # requests in flight that hold a stack being handed over
+MAX_SIDE = 1024                # largest cutout side of a mix this driver runs
+RUNTIME_MARGIN = 8 << 30       # device bytes left to the HIP runtime (scratch, queues)
 
 
 def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=16,
@@ -127,9 +134,21 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
     handle's trajectory slab size (0: the library's default); stage_fp32: a
     reduced-precision stack is decoded into an FP32 copy per request
     (TNO_REQ_STAGE_FP32) instead of searched in place; on_poll(handle) is
-    called after every round of polls."""
+    called after every round of polls.
+
+    Device memory: a key's first request hands its freshly drawn stack to
+    the library by device pointer, and the stack stays allocated here until
+    that request completes.  At most HANDOVERS such requests are in flight
+    (a request that would hand over another stack waits; requests behind it
+    on keys the library holds go ahead), and with budget_gb=0 the library's
+    budget is the free memory less room for those stacks, one more draw and
+    a margin for the HIP runtime."""
     import torch
     pool = StackPool({s.key: (s.side, s.frames) for s in specs}, dtype, device)
+    if budget_gb == 0.0:
+        free, _ = torch.cuda.mem_get_info(torch.device(device))
+        draw = max(side * side * frames for side, frames in pool.shapes.values()) * 4
+        budget_gb = max(free / 4, free - (HANDOVERS + 1) * draw - RUNTIME_MARGIN) / 1e9
     vel_all = torch.from_numpy(bank).to(device)
     known = set()
     staged = {}
@@ -147,15 +166,22 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
-            while queue:
-                s = queue[0]
+            i = 0
+            while i < len(queue):
+                s = queue[i]
+                R = scales = None
+                if s.key not in known:
+                    if sum(v[3] is not None for v in inflight.values()) >= HANDOVERS:
+                        i += 1   # its stack waits for a hand-over to complete
+                        continue
                 sig, times = pool.inputs(s.key)
                 vel = vel_all[torch.from_numpy(s.traj_idx).to(device)].contiguous()
-                R = scales = None
                 if s.key not in known:
                     if staged.get(s.key) is None:
                         staged[s.key] = pool.residuals(s.key)
-                        torch.cuda.synchronize()
+                        # the draw is on torch's stream; the library's streams
+                        # (non-blocking) keep running meanwhile
+                        torch.cuda.current_stream().synchronize()
                     R, scales = staged[s.key]
                 req = tno.make_request(R, sig if R is not None else None, times, vel, dtype=dtype,
                                        scales=scales, top_k=top_k, stack_key=s.key,
@@ -182,7 +208,7 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
                 known.add(s.key)
                 staged.pop(s.key, None)
                 inflight[ticket] = (s, o, vel, R, scales)
-                queue.popleft()
+                del queue[i]
             done = []
             for ticket in list(inflight):
                 rc, res = tno.tno_search_poll(h.h, ticket, 0)
@@ -219,6 +245,12 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
             stats.update({f: getattr(st, f) for f, _ in st._fields_ if f != "reserved"})
     finally:
         h.close()
+        # give the device memory of the stacks and outputs back, so that a
+        # handle created next sees it free (its default budget is a share of
+        # the free memory)
+        del pool, staged, inflight, queue
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
     return recs
 
 
@@ -238,12 +270,19 @@ def main(argv=None):
     ap.add_argument("--keys", type=int, default=12)
     ap.add_argument("--load", type=float, default=0.7, help="arrival rate / back-to-back capacity")
     ap.add_argument("--budget-gb", type=float, default=0.0)
-    ap.add_argument("--max-side", type=int, default=2048)
+    ap.add_argument("--max-side", type=int, default=1024,
+                    help="largest cutout side (at most 1024 px: larger mixes are disabled)")
     ap.add_argument("--dtypes", default="f32,bf16")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--modes", default="eager,batch",
                     help="eager launches, requests run as HIP graphs, and/or batched steps")
     args = ap.parse_args(argv)
+    if args.max_side > MAX_SIDE:
+        # with cutouts to 2048 px this driver's own stack copies and the
+        # library's budget together exhausted device memory: the HIP runtime
+        # aborted its queues (out of resources) and the run hung
+        ap.error("cutouts above %d px are disabled: device memory of the driver's stack copies "
+                 "and the library's budget is not yet bounded together" % MAX_SIDE)
 
     def log(m):
         print("[serve] " + m, file=sys.stderr, flush=True)
