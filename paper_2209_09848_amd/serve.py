@@ -291,14 +291,17 @@ def main(argv=None):
     sides = [s for s in range(256, args.max_side + 1, 256)]
     shapes = draw_stack_shapes(args.keys, args.seed, sides=sides)
     specs = draw_requests(args.requests + args.warm, shapes, bank.shape[0], args.seed)
-    # capacity: back-to-back service rate of the FP32 form on a sample of the mix
-    cal = [Spec(s.key, s.side, s.frames, s.traj_idx, 0.0) for s in specs[:12]]
+    # capacity: updates/s of the plain FP32 search back to back on a sample of
+    # the mix; arrivals offer `load` times that in the mix's mean work
+    cal = [Spec(s.key, s.side, s.frames, s.traj_idx, 0.0) for s in specs[:16]]
     log("calibrating back-to-back capacity on %d requests" % len(cal))
     crec = run_stream(cal, bank, dtype="f32", budget_gb=args.budget_gb, max_inflight=1)
-    mean_s = float(np.mean([x["device_ms"] for x in crec])) * 1e-3
-    rate = args.load / mean_s
-    log("mean device time %.1f ms -> arrival rate %.2f req/s" % (mean_s * 1e3, rate))
-    out = {"load": args.load, "arrival_rate_per_s": rate, "forms": {}}
+    cap = sum(x["updates"] for x in crec) / (sum(x["device_ms"] for x in crec) * 1e-3)
+    mean_u = float(np.mean([len(s.traj_idx) * s.side * s.side * s.frames for s in specs]))
+    rate = args.load * cap / mean_u
+    log("capacity %.3g updates/s, mean %.3g updates per request -> arrival rate %.2f req/s"
+        % (cap, mean_u, rate))
+    out = {"load": args.load, "arrival_rate_per_s": rate, "capacity_updates_per_s": cap, "forms": {}}
     for dt in args.dtypes.split(","):
         for mode in args.modes.split(","):
             sp = poisson_arrivals([Spec(s.key, s.side, s.frames, s.traj_idx) for s in specs], rate,
