@@ -221,6 +221,8 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
                 rec = {"key": s.key, "side": s.side, "frames": s.frames,
                        "traj": int(len(s.traj_idx)), "arrival": s.arrival, "done": t_done,
                        "latency_ms": (t_done - s.arrival) * 1e3, "device_ms": res.device_ms,
+                       "prep_ms": res.prep_ms, "table_ms": res.table_ms, "lambda_ms": res.lambda_ms,
+                       "search_ms": res.search_ms, "reduce_ms": res.reduce_ms, "queue_ms": res.queue_ms,
                        "updates": int(res.updates),
                        "topk": tno.decode_candidates(inflight[ticket][1]["topk"], res.n_topk)}
                 if keep:
