@@ -89,7 +89,17 @@ extern "C" {
                                        preparation and reductions run on its pool stream.
                                        Results are bit-identical to unbatched requests.  Needs
                                        the own stream pool (stream NULL) and excludes GRAPHS;
-                                       steps are formed whenever submit or poll is called. */
+                                       steps are formed whenever submit or poll is called, so
+                                       the caller's thread must not stall: combine with
+                                       TNO_CFG_RESERVE. */
+
+#define TNO_CFG_RESERVE 8u          /* reserve the whole HBM budget at create as one device block
+                                       and carve every request's arena and resident stack from it:
+                                       no device allocation or free after create (a large one can
+                                       hold the calling thread for hundreds of ms, which stalls
+                                       batched steps, launched from submit and poll).  Other users
+                                       of the GPU see the budget as taken.  TNO_E_NOMEM from create
+                                       if the block cannot be had. */
 
 /* tno_request.flags */
 #define TNO_REQ_DEVICE_PTRS 1u      /* every input and output pointer is device memory */

@@ -6,6 +6,10 @@
 
 #include "../../include/tno_search.h"
 
+#include <cstddef>
+#include <iterator>
+#include <map>
+
 namespace tno {
 
 // Search tile shapes.  A lane owns CPL adjacent columns x RPL rows; a block
@@ -217,5 +221,72 @@ constexpr int TOPK_CHUNK = 8192;
 
 // Set the thread's last-error message (read by tno_search_last_error).
 void record_error(const char *fmt, ...);
+
+// Byte ranges of one device block reserved at handle creation
+// (TNO_CFG_RESERVE): best fit over the free ranges, which are kept by offset
+// and merged with their neighbours when a range comes back, so that every
+// request's arena and every resident stack is carved from the block without a
+// device allocation.  Sizes are rounded up to GRAIN (a multiple of the
+// arenas' 256-byte alignment).  Host logic only.
+class OffsetPool {
+  public:
+    static constexpr size_t GRAIN = size_t(2) << 20;
+    static constexpr size_t NONE = ~size_t(0);
+
+    void reset(size_t bytes)
+    {
+        free_.clear();
+        total_ = bytes / GRAIN * GRAIN;
+        if (total_)
+            free_[0] = total_;
+    }
+    size_t total() const { return total_; }
+    size_t free_bytes() const
+    {
+        size_t n = 0;
+        for (const auto &kv : free_)
+            n += kv.second;
+        return n;
+    }
+    size_t ranges() const { return free_.size(); }
+    // Offset of a range of at least `bytes` (its size in *got), or NONE.
+    size_t take(size_t bytes, size_t *got)
+    {
+        const size_t need = (bytes + GRAIN - 1) / GRAIN * GRAIN;
+        auto best = free_.end();
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= need && (best == free_.end() || it->second < best->second))
+                best = it;
+        if (need == 0 || best == free_.end())
+            return NONE;
+        const size_t off = best->first, size = best->second;
+        free_.erase(best);
+        if (size > need)
+            free_[off + need] = size - need;
+        *got = need;
+        return off;
+    }
+    // Return a range that take() handed out.
+    void give(size_t off, size_t bytes)
+    {
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + bytes == next->first) {
+            bytes += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += bytes;
+                return;
+            }
+        }
+        free_[off] = bytes;
+    }
+
+  private:
+    std::map<size_t, size_t> free_;   // offset -> size of each free range
+    size_t total_ = 0;
+};
 
 }  // namespace tno

@@ -692,6 +692,10 @@ struct tno_search {
     int device = 0;
     std::vector<hipStream_t> streams;
     bool own_streams = false;
+    // TNO_CFG_RESERVE: the budget as one device block, arenas and resident
+    // stacks carved from it (no device allocation or free after create)
+    void *pool_base = nullptr;
+    tno::OffsetPool pool;
     unsigned next_stream = 0;
     uint64_t budget = 0;
     uint64_t in_use = 0;               // device blocks held by live requests and resident stacks
@@ -778,6 +782,16 @@ int hip_fail(hipError_t e, const char *what, char *msg, size_t n)
 
 template <class T> T *at(void *arena, size_t off) { return (T *)((char *)arena + off); }
 
+// A block no longer held: back to the reserved block's free ranges, or to
+// the cache of blocks kept for reuse.
+void keep_block(tno_search *h, void *p, size_t bytes)
+{
+    if (h->pool_base)
+        h->pool.give((size_t)((char *)p - (char *)h->pool_base), bytes);
+    else
+        h->cache.put(p, bytes);
+}
+
 // Make `need` bytes of budget available: evict idle resident stacks (least
 // recently used first), then shrink the block cache so that live memory plus
 // cached blocks stay within the budget.  Returns false if it cannot.
@@ -791,7 +805,7 @@ bool make_room(tno_search *h, size_t need)
         if (!victim)
             return false;
         h->stacks.erase(victim->key);
-        h->cache.put(victim->block, victim->block_bytes);
+        keep_block(h, victim->block, victim->block_bytes);
         h->in_use -= victim->bytes;
         if (victim->ready)
             (void)hipEventDestroy(victim->ready);
@@ -812,7 +826,10 @@ bool evict_one(tno_search *h)
     if (!victim)
         return false;
     h->stacks.erase(victim->key);
-    (void)hipFree(victim->block);
+    if (h->pool_base)
+        keep_block(h, victim->block, victim->block_bytes);
+    else
+        (void)hipFree(victim->block);
     h->in_use -= victim->bytes;
     if (victim->ready)
         (void)hipEventDestroy(victim->ready);
@@ -826,6 +843,19 @@ bool evict_one(tno_search *h)
 // before the allocation is given up.
 void *get_block(tno_search *h, size_t bytes, size_t *got)
 {
+    if (h->pool_base) {
+        // reserved: a range of the handle's block (idle resident stacks give
+        // theirs back, least recently used first, when none fits)
+        if (++h->n_alloc == h->fault_alloc)
+            return nullptr;           // injected failure (TNO_FAULT=alloc:N)
+        for (;;) {
+            const size_t off = h->pool.take(bytes, got);
+            if (off != tno::OffsetPool::NONE)
+                return (char *)h->pool_base + off;
+            if (!evict_one(h))
+                return nullptr;
+        }
+    }
     void *p = h->cache.take(bytes, got);
     if (p)
         return p;
@@ -1426,7 +1456,7 @@ void release(tno_search *hd, Request *q)
     if (q->exec)
         hd->free_execs.emplace(q->exec_key, q->exec);
     if (q->arena) {
-        hd->cache.put(q->arena, q->arena_bytes);
+        keep_block(hd, q->arena, q->arena_bytes);
         hd->in_use -= q->arena_bytes;
     }
     if (q->stack) {
@@ -1525,7 +1555,7 @@ int tno_search_create(const tno_config *cfg, tno_search **out_handle)
         set_last(fail(TNO_E_INVAL, "config.reserved must be 0"));
         return TNO_E_INVAL;
     }
-    if ((cfg->flags & ~(TNO_CFG_GRAPHS | TNO_CFG_AUTOTUNE | TNO_CFG_BATCH)) != 0) {
+    if ((cfg->flags & ~(TNO_CFG_GRAPHS | TNO_CFG_AUTOTUNE | TNO_CFG_BATCH | TNO_CFG_RESERVE)) != 0) {
         set_last(fail(TNO_E_INVAL, "unknown config flags 0x%x", cfg->flags));
         return TNO_E_INVAL;
     }
@@ -1573,6 +1603,20 @@ int tno_search_create(const tno_config *cfg, tno_search **out_handle)
         return hip_fail(e, "hipMemGetInfo", nullptr, 0);
     }
     h->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
+    if (cfg->flags & TNO_CFG_RESERVE) {
+        // the whole budget now, as one block: a large hipMalloc or hipFree can
+        // hold the host for hundreds of ms (seconds, measured), which a
+        // serving loop cannot afford between its polls
+        h->pool.reset(h->budget);
+        h->budget = h->pool.total();
+        if (h->budget == 0 || (e = hipMalloc(&h->pool_base, h->budget)) != hipSuccess) {
+            (void)hipGetLastError();
+            h->pool_base = nullptr;
+            set_last(fail(TNO_E_NOMEM, "reserving the HBM budget of %.3g GB failed", h->budget / 1e9));
+            tno_search_destroy(h);
+            return TNO_E_NOMEM;
+        }
+    }
     if (const char *fe = getenv("TNO_FAULT")) {
         // test hook: "alloc:N" makes the N-th fresh device allocation of this
         // handle fail as if the device were out of memory
@@ -1772,7 +1816,7 @@ int tno_search_submit(tno_search *h, const tno_request *req, const tno_outputs *
             (void)hipStreamSynchronize(q->stream);
             if (ns->ready)
                 (void)hipEventDestroy(ns->ready);
-            h->cache.put(blk, got);
+            keep_block(h, blk, got);
             delete ns;
             release(h, q);
             return hip_fail(e, "staging a resident stack", nullptr, 0);
@@ -2031,13 +2075,15 @@ void tno_search_destroy(tno_search *h)
             (void)hipGraphExecDestroy(kv.second);
         h->free_execs.clear();
         for (auto &kv : h->stacks) {
-            h->cache.put(kv.second->block, kv.second->block_bytes);
+            keep_block(h, kv.second->block, kv.second->block_bytes);
             if (kv.second->ready)
                 (void)hipEventDestroy(kv.second->ready);
             delete kv.second;
         }
         h->stacks.clear();
         h->cache.trim(0);
+        if (h->pool_base)
+            (void)hipFree(h->pool_base);
         if (h->own_streams)
             for (hipStream_t s : h->streams)
                 (void)hipStreamDestroy(s);

@@ -125,7 +125,7 @@ RUNTIME_MARGIN = 8 << 30       # device bytes left to the HIP runtime (scratch, 
 
 def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=16,
                max_inflight=8, log=None, mode="eager", keep=False, stats=None, slab_bytes=0,
-               stage_fp32=False, on_poll=None):
+               stage_fp32=False, on_poll=None, reserve=True):
     """Serve `specs` in arrival order; mode "eager" (each request's kernels on
     a pool stream), "graphs" (each request as a HIP graph) or "batch" (the
     searches of admitted requests share steps).  Returns per-request records
@@ -142,7 +142,9 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
     (a request that would hand over another stack waits; requests behind it
     on keys the library holds go ahead), and with budget_gb=0 the library's
     budget is the free memory less room for those stacks, one more draw and
-    a margin for the HIP runtime."""
+    a margin for the HIP runtime.  reserve: the handle takes that budget at
+    creation as one block (TNO_CFG_RESERVE), so that no submit waits on a
+    device allocation."""
     import torch
     pool = StackPool({s.key: (s.side, s.frames) for s in specs}, dtype, device)
     if budget_gb == 0.0:
@@ -158,7 +160,7 @@ def run_stream(specs, bank, dtype="bf16", budget_gb=0.0, device="cuda:0", top_k=
     inflight = {}
     h = tno.Search(0, own_streams=True, max_inflight=max_inflight,
                    hbm_budget_bytes=int(budget_gb * 1e9), graphs=mode == "graphs", batch=mode == "batch",
-                   slab_bytes=slab_bytes)
+                   slab_bytes=slab_bytes, reserve=reserve)
     t0 = time.perf_counter()
     retried = False
     try:

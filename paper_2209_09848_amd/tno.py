@@ -31,6 +31,7 @@ TNO_MAX_TABLE_Q = 64
 TNO_CFG_GRAPHS = 1
 TNO_CFG_AUTOTUNE = 2
 TNO_CFG_BATCH = 4
+TNO_CFG_RESERVE = 8
 SEARCH_VARIANTS = ("w4c2", "w8c2", "w2c2", "w4c1", "w8c1", "w4c4", "w2c2r16", "w4c2r16", "ws", "ws4")
 TNO_REQ_DEVICE_PTRS = 1
 TNO_REQ_VALIDATE = 2
@@ -288,13 +289,14 @@ class Search:
     def __init__(self, device: int = 0, max_inflight: int = 64, hbm_budget_bytes: int = 0,
                  stream=None, own_streams: bool = False, autotune: bool = False,
                  tune_cache_path: str | None = None, graphs: bool = False, batch: bool = False,
-                 slab_bytes: int = 0):
+                 slab_bytes: int = 0, reserve: bool = False):
         """own_streams=True: the library runs requests on its own pool of streams
         (concurrent requests overlap; inputs must be complete before submit);
         otherwise every request runs on `stream` (default: torch's current).
         batch=True (implies own_streams): continuous batching of the searches
         of admitted requests into shared steps.  slab_bytes: device bytes of a
-        trajectory slab (0: the library's default)."""
+        trajectory slab (0: the library's default).  reserve=True: the HBM
+        budget is reserved at creation and every device buffer carved from it."""
         import torch
         if own_streams or batch:
             stream = 0
@@ -305,7 +307,7 @@ class Search:
         cfg.max_inflight = max_inflight
         cfg.hbm_budget_bytes = hbm_budget_bytes
         cfg.flags = ((TNO_CFG_AUTOTUNE if autotune else 0) | (TNO_CFG_GRAPHS if graphs else 0) |
-                     (TNO_CFG_BATCH if batch else 0))
+                     (TNO_CFG_BATCH if batch else 0) | (TNO_CFG_RESERVE if reserve else 0))
         cfg.reserved = 0
         cfg.stream = ctypes.c_void_p(stream) if stream else None
         self._path = tune_cache_path.encode() if tune_cache_path else None

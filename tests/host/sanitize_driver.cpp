@@ -89,6 +89,52 @@ static void fill(Case &c, int H, int W, int T, int J, std::mt19937_64 &g)
     c.req.velocities = c.vel.data();
 }
 
+// The reserved-block allocator: random takes and gives never hand out
+// overlapping ranges, keep the byte count, refuse what does not fit, and
+// merge every range back into one when all are given back.
+static int check_offset_pool(std::mt19937_64 &g)
+{
+    const size_t G = tno::OffsetPool::GRAIN;
+    tno::OffsetPool pool;
+    pool.reset(1000 * G + 123);
+    if (pool.total() != 1000 * G || pool.free_bytes() != pool.total() || pool.ranges() != 1)
+        return 20;
+    struct Held { size_t off, size; };
+    std::vector<Held> held;
+    size_t got = 0;
+    if (pool.take(1001 * G, &got) != tno::OffsetPool::NONE || pool.take(0, &got) != tno::OffsetPool::NONE)
+        return 21;
+    for (int it = 0; it < 20000; ++it) {
+        if (held.empty() || g() % 3 != 0) {
+            const size_t want = 1 + g() % (40 * G);
+            const size_t off = pool.take(want, &got);
+            if (off == tno::OffsetPool::NONE)
+                continue;
+            if (got < want || got % G != 0 || off % G != 0 || off + got > pool.total())
+                return 22;
+            for (const Held &h : held)
+                if (off < h.off + h.size && h.off < off + got)
+                    return 23;
+            held.push_back({off, got});
+        } else {
+            const size_t i = g() % held.size();
+            pool.give(held[i].off, held[i].size);
+            held[i] = held.back();
+            held.pop_back();
+        }
+        size_t in_use = 0;
+        for (const Held &h : held)
+            in_use += h.size;
+        if (in_use + pool.free_bytes() != pool.total())
+            return 24;
+    }
+    for (const Held &h : held)
+        pool.give(h.off, h.size);
+    if (pool.free_bytes() != pool.total() || pool.ranges() != 1)
+        return 25;
+    return 0;
+}
+
 int main()
 {
     std::mt19937_64 g(2209);
@@ -151,6 +197,8 @@ int main()
         return 5;
     if (tno_search_footprint(nullptr, nullptr) != 0)
         return 6;
-    printf("host sanitizer driver: %d valid, %d refused\n", ok, refused);
+    if (int rc = check_offset_pool(g))
+        return rc;
+    printf("host sanitizer driver: %d valid, %d refused; offset pool checked\n", ok, refused);
     return 0;
 }

@@ -10,6 +10,7 @@ kernel runs normally.
   be neither polled nor cancelled again; the other tickets of the handle finish
   with the oracle's results, with eager launches and with batched steps.
 * Destroying a handle with tickets still live drains them; a new handle works.
+* A handle that reserves its budget at creation carves every buffer from it.
 """
 import os
 
@@ -43,8 +44,8 @@ def _problem(seed, T=24, H=40, W=72, J=3):
 class _Req:
     """A request on the GPU, its outputs and the oracle's answer."""
 
-    def __init__(self, seed):
-        self.R, self.sigma, self.times, self.vel = _problem(seed)
+    def __init__(self, seed, **shape):
+        self.R, self.sigma, self.times, self.vel = _problem(seed, **shape)
         self.t = [_to(self.R), _to(self.sigma), _to(self.times), _to(self.vel)]
         T, H, W = self.R.shape
         self.req = tno.make_request(*self.t, t_ref=float(self.times[0]), top_k=K)
@@ -130,3 +131,31 @@ def test_destroy_with_live_tickets_drains_them():
     with tno.Search(0) as h2:
         assert h2.wait(h2.submit(reqs[0].req, reqs[0].out)).status == tno.TNO_OK
     reqs[0].check()
+
+
+def test_reserved_handle_carves_its_buffers_from_one_block():
+    """TNO_CFG_RESERVE: the budget is taken at creation; requests of several
+    shapes run from ranges of that block with the bits of an unreserved
+    handle, nothing is charged once they are collected, and a request larger
+    than the block is refused."""
+    reqs = [_Req(30 + i) for i in range(3)]
+    with tno.Search(0) as h:
+        for r in reqs:
+            assert h.wait(h.submit(r.req, r.out)).status == tno.TNO_OK
+    ref = [r.o["snr"].cpu().numpy().copy() for r in reqs]
+    with tno.Search(0, own_streams=True, reserve=True, hbm_budget_bytes=1 << 30) as h:
+        print("reserved handle, 3 requests", flush=True)
+        st = tno.tno_search_stats(h.h)
+        assert st.budget_bytes == 1 << 30 and st.in_use_bytes == 0
+        tickets = [h.submit(r.req, r.out) for r in reqs]
+        for t in tickets:
+            assert h.wait(t).status == tno.TNO_OK
+        for r, s in zip(reqs, ref):
+            assert np.array_equal(r.o["snr"].cpu().numpy(), s)
+        reqs[0].check()
+        st = tno.tno_search_stats(h.h)
+        assert st.inflight == 0 and st.in_use_bytes == 0 and st.cached_bytes == 0
+    big = _Req(40, T=64, H=128, W=256)    # its staged stack alone is ≈ 9 MB
+    with tno.Search(0, reserve=True, hbm_budget_bytes=2 << 20) as h:
+        rc, t = tno.tno_search_submit(h.h, big.req, big.out)
+        assert rc == tno.TNO_E_NOMEM and t is None

@@ -1,4 +1,5 @@
-"""The runtime's host code (validation, planning, footprint) built with
+"""The runtime's host code (validation, planning, footprint, the reserved-block
+allocator) built with
 AddressSanitizer and UndefinedBehaviorSanitizer and driven over edge cases and
 seeded random requests (tests/host/sanitize_driver.cpp).  CPU only: the device
 launch wrappers are stubs in the driver."""
@@ -31,4 +32,4 @@ def test_runtime_host_code_under_asan_ubsan(tmp_path):
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
-    assert "valid" in r.stdout
+    assert "valid" in r.stdout and "offset pool checked" in r.stdout
